@@ -1,0 +1,210 @@
+"""Benchmark: lattice H-matrix-vector products per second on one MI355X.
+
+Workload: planar 30-degree dipping thrust fault of 480 x 256 squares of 50 m
+(N = 122880), full-space coplanar kernel (mu = 32 GPa, nu = 0.25), ACA
+eps = 1e-5, leaf 64, eta = 2, lattice 32 x 32; slip rates log-uniform in
+[1e-12, 1e-9] m/s from seed 2.  One step is one H-matrix-vector product
+y = H x (gather through the cluster permutation, dense near-field blocks,
+both low-rank phases, row-owned accumulation, scatter back).
+
+The headline value is the FP32-stored / FP64-accumulated batched product;
+the plain FP64 product and the batched FP64 product are timed beside it.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "H-matvec/s and % of HBM peak at N≈1.2e5, FP32-batched vs FP64-plain, rel err ≤2e-5"
+WORKLOAD = "dip30_480x256"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def time_products(torch, H, x, y, steps, warmup):
+    """Returns (ms per product over the timed region, mean launch duration in ms
+    from per-product HIP events on the launch stream)."""
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        H.matvec(x, y=y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        H.matvec(x, y=y)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / steps
+    region = ev0.elapsed_time(ev1) / steps
+    # per-launch durations: each product bracketed by its own events
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    for a, b in evs:
+        a.record(stream)
+        H.matvec(x, y=y)
+        b.record(stream)
+    torch.cuda.synchronize()
+    per = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    return max(region, 1e-9), per, wall
+
+
+def cpu_baseline(f, w, x, y_gpu):
+    """Oracle H-matrix product timed on a bounded sample: the complete
+    lattice block-rows 0 and 15 (2 of 32, 7680 of 122880 rows), built by the
+    oracle's own ACA, applied repeatedly for about 15 s with one BLAS thread;
+    scaled to full products by the row fraction."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.greens import CoplanarRectGeometry
+    from oracle.hmatrix import HMatrix as OracleH
+    from synth.faults import MU, NU
+
+    g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
+    rows_sel = (0, 15)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        H = OracleH.build(g, w["leaf"], w["eta"], w["aca_eps"], w["lattice"], lattice_rows=rows_sel)
+        build_s = time.perf_counter() - t0
+        H.matvec(x)
+        reps, t0 = 0, time.perf_counter()
+        while True:
+            y = H.matvec(x)
+            reps += 1
+            el = time.perf_counter() - t0
+            if el > 15.0:
+                break
+    per_sample = el / reps
+    lat_rows = H.lattice_row_ranges(rows_sel)
+    nrows = sum(e - s for s, e in lat_rows)
+    scale = f.n / nrows
+    # compare the oracle's sampled rows with the GPU product on the same rows
+    idx = np.concatenate([H.perm[s:e] for s, e in lat_rows])
+    err = float(np.linalg.norm(y[idx] - y_gpu[idx]) / np.linalg.norm(y[idx]))
+    cpu = open("/proc/cpuinfo").read()
+    model = next((l.split(":", 1)[1].strip() for l in cpu.splitlines() if l.startswith("model name")), "unknown")
+    return {
+        "value": 1.0 / (per_sample * scale), "unit": "matvec/s", "cores": 1, "kind": "oracle",
+        "sample": (f"oracle FP64 H-matrix product (NumPy block loop, 1 BLAS thread) over lattice block-rows "
+                   f"{list(rows_sel)} = {nrows} of {f.n} rows, {reps} products in {el:.1f} s, scaled by "
+                   f"{scale:.1f}; oracle build of the sample {build_s:.1f} s (untimed)"),
+        "cpu_model": model, "host_threads_available": len(os.sched_getaffinity(0)),
+        "sample_rel_err_gpu_f32_vs_oracle": err,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="batched_f32,plain_f64,batched_f64")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: the product is not sharded across GPUs in this build "
+              "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2110_12165_amd as hm
+    from paper_2110_12165_amd.tuning import bench_options
+    from synth import WORKLOADS, config_fault, loguniform_rates
+    from synth.faults import MU, NU
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    w = WORKLOADS[WORKLOAD]
+    f = config_fault(WORKLOAD)
+    x_np = loguniform_rates(f.n, w["seed"])
+    x = torch.tensor(x_np, device=dev)
+    results = {}
+    outputs = {}
+    for variant in args.variants.split(","):
+        opts = bench_options(WORKLOAD, variant)
+        t0 = time.perf_counter()
+        H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, **opts)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        info = H.info()
+        y = torch.empty_like(x)
+        log(f"[bench] {variant}: built in {build_s:.1f} s; kernel {info['kernel']}, "
+            f"{info['factor_bytes'] / 1e9:.3f} GB of factors")
+        ms, launch_ms, wall_ms = time_products(torch, H, x, y, args.steps, args.warmup)
+        outputs[variant] = H.matvec(x).cpu().numpy()
+        achieved = info["alg_bytes"] / (launch_ms * 1e-3) / 1e9
+        results[variant] = dict(ms=ms, launch_ms=launch_ms, wall_ms=wall_ms, matvec_per_s=1e3 / ms,
+                                alg_bytes=info["alg_bytes"], achieved_gbs=achieved,
+                                hbm_frac=achieved / HBM_PEAK_GBS, build_s=build_s, info=info)
+        log(f"[bench] {variant}: {1e3 / ms:.1f} matvec/s, launch {launch_ms * 1e3:.1f} us, "
+            f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM)")
+        H.close()
+        torch.cuda.empty_cache()
+
+    head = results["batched_f32"]
+    info = head["info"]
+    line = {
+        "metric": METRIC,
+        "value": head["matvec_per_s"],
+        "unit": "matvec/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": WORKLOAD, "N": f.n,
+            "geometry": "planar 30-deg dipping thrust, 480 x 256 squares of 50 m, full-space coplanar kernel",
+            "aca_eps": w["aca_eps"], "leaf": w["leaf"], "eta": w["eta"], "lattice": w["lattice"],
+            "x": "log-uniform [1e-12, 1e-9] m/s, seed 2",
+            "factor_storage": "f32", "accumulate": "f64", "kernel": info["kernel"],
+            "wg_waves": info["wg_waves"],
+            "parallelism": "single GPU",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": head["achieved_gbs"],
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": head["hbm_frac"],
+            "traffic": None,
+        },
+        "hmat": {k: info[k] for k in ("n_dense", "n_lr", "dense_entries", "lr_entries", "max_rank", "sum_rank",
+                                      "factor_bytes", "alg_bytes", "n_units_p1", "n_units_p2")},
+    }
+    for v, r in results.items():
+        line[v] = {k: r[k] for k in ("matvec_per_s", "ms", "launch_ms", "achieved_gbs", "hbm_frac", "build_s")}
+        line[v]["kernel"] = r["info"]["kernel"]
+    if "plain_f64" in results:
+        line["speedup_batched_f32_vs_plain_f64"] = head["matvec_per_s"] / results["plain_f64"]["matvec_per_s"]
+    if "batched_f64" in outputs:
+        ref = outputs["batched_f64"]
+        line["rel_diff_f32_vs_f64_gpu"] = float(np.linalg.norm(outputs["batched_f32"] - ref) / np.linalg.norm(ref))
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (oracle sample) ...")
+        line["cpu_baseline"] = cpu_baseline(f, w, x_np, outputs["batched_f32"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,260 @@
+/*
+ * hmat.h — lattice H-matrix library for boundary-element earthquake-sequence
+ * models on AMD Instinct MI355X (gfx950).
+ *
+ * The library builds a lattice H-matrix approximation of an element
+ * stiffness matrix and applies it to slip-rate vectors on the GPU.
+ *
+ *   Method (Ozawa, Ida, Hoshino, Ando, "Large-scale earthquake sequence
+ *   simulations on 3D nonplanar faults using the boundary element method
+ *   accelerated by lattice H-matrices"):
+ *     - stiffness entries: section 2.1, eqs. (5)-(6)
+ *     - cluster tree, admissibility, partition: section 3.1.1, eq. (17)
+ *     - adaptive cross approximation: section 3.1.2, eqs. (18)-(19)
+ *     - H-matrix-vector product: section 3.1.3, eq. (20)
+ *     - lattice structure: section 3.2
+ *     - rate-and-state right-hand side: section 2.2, eqs. (7)-(13), (21)-(22)
+ *
+ * Conventions shared by every entry point
+ *   - Every call returns hmat_status: HMAT_OK (0) or a negative error code.
+ *     No C++ exception crosses this interface.  After an error,
+ *     hmat_last_error() returns a message for the calling thread.
+ *   - A handle (hmat_t) owns all device memory it allocates: factor storage,
+ *     block descriptors, schedules and scratch.  The caller owns every array
+ *     passed in; the library never frees or retains caller pointers beyond
+ *     the call (except where stated).
+ *   - "Device" pointers are addresses returned by hipMalloc (or a PyTorch
+ *     CUDA/HIP tensor's data_ptr()) on the device that was current when the
+ *     handle was created.  "Host" pointers are ordinary process memory.
+ *   - Calls that take a stream are stream-ordered on that hipStream_t
+ *     (NULL = the null stream): they enqueue work and return without waiting
+ *     for the GPU, unless stated otherwise.
+ *   - A handle is not safe to use from two streams or threads at once: its
+ *     products share one scratch buffer.
+ *   - Vectors at the interface are FP64 in the caller's element order.
+ */
+#ifndef HMAT_H_
+#define HMAT_H_
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hmat_s* hmat_t;
+
+typedef enum {
+  HMAT_OK = 0,
+  HMAT_EINVAL = -1,       /* invalid argument (null pointer, bad size, bad option, bad mesh) */
+  HMAT_ENOMEM = -2,       /* host or device allocation failed */
+  HMAT_EDEVICE = -3,      /* a HIP runtime call failed (message names it) */
+  HMAT_ESTATE = -4,       /* handle in an unusable state */
+  HMAT_EUNSUPPORTED = -5  /* valid request this build does not implement */
+} hmat_status;
+
+/* Storage precision of the factors on the device.  Products always take and
+ * return FP64 vectors and accumulate in FP64. */
+typedef enum { HMAT_F64 = 0, HMAT_F32 = 1 } hmat_prec;
+
+/* Product kernel.
+ *   HMAT_KERNEL_PLAIN:   two launches over the block list in its natural
+ *                        layout (column-major dense blocks and factors).
+ *   HMAT_KERNEL_BATCHED: blocks repacked into lane-coalesced panels and
+ *                        processed as one list of work units: two launches
+ *                        (SPLIT) or one persistent launch (PERSISTENT).
+ *   HMAT_KERNEL_AUTO:    BATCHED with the schedule picked by hmat_autotune. */
+typedef enum {
+  HMAT_KERNEL_PLAIN = 0,
+  HMAT_KERNEL_BATCHED_SPLIT = 1,
+  HMAT_KERNEL_BATCHED_PERSISTENT = 2,
+  HMAT_KERNEL_AUTO = 3
+} hmat_kernel;
+
+/* Green's function families. */
+typedef enum {
+  /* Unbounded isotropic medium, all elements rectangles in one plane, slip
+   * along a common in-plane direction (closed form; eqs. (5)-(6) with the
+   * full-space kernel).  The normal-stress matrix B of such a fault is 0. */
+  HMAT_GF_FS_RECT_COPLANAR = 1
+} hmat_green_kind;
+
+/* Element mesh (host memory, read during hmat_build only). */
+typedef struct {
+  int64_t n;               /* number of elements, >= 1 */
+  int32_t nvert;           /* vertices per element: 4 (rectangles) */
+  const double* verts;     /* n * nvert * 3 coordinates [m], element-major;
+                              counter-clockwise seen from the +normal side */
+  const double* slip_dir;  /* n * 3 unit slip directions in the element plane */
+} hmat_mesh;
+
+typedef struct {
+  int32_t kind;            /* hmat_green_kind */
+  int32_t component;       /* 0: shear traction along the slip direction (A),
+                              1: normal traction, compression positive (B) */
+  double mu;               /* rigidity [Pa] */
+  double nu;               /* Poisson ratio, in (-1, 0.5) */
+} hmat_green;
+
+typedef struct {
+  double aca_eps;          /* ACA tolerance of eq. (19), > 0 */
+  double eta;              /* admissibility parameter of eq. (17), > 0 */
+  int32_t leaf;            /* maximum cluster size of a tree leaf, >= 1 */
+  int32_t lattice;         /* lattice blocks per side (power of two); 1 = normal H-matrix */
+  int32_t max_rank;        /* rank cap before the dense fallback; 0 = min(m, n) / 2 */
+  int32_t prec;            /* hmat_prec: factor storage on the device */
+  int32_t kernel;          /* hmat_kernel */
+  int32_t n_threads;       /* host threads for the build; 0 = all hardware threads */
+  int32_t wg_waves;        /* BATCHED: waves per workgroup (4, 8 or 16); 0 = default */
+  int32_t unit_kib;        /* BATCHED: target bytes per work unit in KiB; 0 = default */
+} hmat_opts;
+
+/* Fill *opts with defaults (eps 1e-6, eta 2, leaf 32, lattice 1, FP64, AUTO). */
+void hmat_default_opts(hmat_opts* opts);
+
+/* Statistics of a handle (hmat_info). */
+typedef struct {
+  int64_t n;               /* matrix order */
+  int64_t n_dense;         /* dense (inadmissible) blocks */
+  int64_t n_lr;            /* low-rank blocks (rank 0 blocks included) */
+  int64_t dense_entries;   /* sum m*n over dense blocks */
+  int64_t lr_entries;      /* sum r*(m+n) over low-rank blocks */
+  int64_t max_rank;
+  int64_t sum_rank;        /* total rank = length of the intermediate vector t */
+  int64_t n_leaves;        /* row units of the product (leaf row clusters) */
+  int64_t tree_depth;
+  int64_t device_bytes;    /* device memory held by the handle */
+  int64_t factor_bytes;    /* bytes of stored factors read per product: s*(dense+lr entries) */
+  int64_t alg_bytes;       /* algorithmic bytes per single-vector product:
+                              factor_bytes + 8N (x) + 16N (y read+write) + 4N (perm) */
+  int64_t n_units_p1;      /* BATCHED: work units of phase 1 (t = V^T x) */
+  int64_t n_units_p2;      /* BATCHED: work units of phase 2 (y = D x + U t) */
+  int32_t prec;
+  int32_t kernel;          /* kernel actually used (AUTO resolved) */
+  int32_t wg_waves;
+  int32_t lattice;
+} hmat_stats;
+
+/* Host copy of the blocks of a handle, in cluster order (hmat_export /
+ * hmat_import).  Block b occupies rows [r0, r0+m) and columns [c0, c0+n) of
+ * the cluster-ordered matrix; cluster position k is user element perm[k].
+ *   desc[6*b + 0] = kind (0 dense, 1 low rank)
+ *   desc[6*b + 1..5] = r0, m, c0, n, rank (0 for dense)
+ *   off[b] = first value of the block in values[]:
+ *     dense:    m*n values, column-major;
+ *     low rank: U (m x rank, column-major) then V (n x rank, column-major),
+ *               block = U V^T (the paper's g = U^T, h = V^T, eq. (18)). */
+typedef struct {
+  int64_t n;
+  int64_t nblocks;
+  int64_t nvalues;
+  const int32_t* perm;     /* n */
+  const int64_t* desc;     /* 6 * nblocks */
+  const int64_t* off;      /* nblocks */
+  const double* values;    /* nvalues */
+} hmat_host_blocks;
+
+/*
+ * hmat_build — construct the lattice H-matrix of one stiffness matrix.
+ * Section 3.1.1 (cluster tree on element centres, eq. (17) admissibility),
+ * section 3.2 (lattice: tree cut at depth log2(lattice), each lattice block
+ * partitioned on its own), section 3.1.2 (ACA, eqs. (18)-(19), FP64 on host
+ * threads), then packing and upload of the factors to the current device.
+ *   mesh, green, opts: host structs, validated (EINVAL on any bad field,
+ *     non-finite coordinate, non-planar or non-rectangular element for the
+ *     coplanar kernel, lattice not a power of two or deeper than the tree).
+ *   stream: hipStream_t for the uploads; the call returns after they finish.
+ *   out: receives the new handle; untouched on error.
+ */
+hmat_status hmat_build(const hmat_mesh* mesh, const hmat_green* green, const hmat_opts* opts,
+                       void* stream, hmat_t* out);
+
+/*
+ * hmat_build_host — the construction of hmat_build (same validation, same
+ * blocks) without any device work: the handle holds only the FP64 host
+ * blocks, for hmat_export / hmat_info / hmat_destroy, e.g. to build on a
+ * machine without a GPU and hmat_import elsewhere.  Products, rs_rhs and
+ * hmat_autotune on such a handle return HMAT_ESTATE.
+ */
+hmat_status hmat_build_host(const hmat_mesh* mesh, const hmat_green* green, const hmat_opts* opts, hmat_t* out);
+
+/*
+ * hmat_import — create a handle from host blocks (layout of hmat_host_blocks)
+ * instead of building them; opts selects prec/kernel/schedule (the
+ * construction fields are ignored).  Blocks must tile the n x n matrix
+ * exactly once and perm must be a permutation (EINVAL otherwise).  The
+ * arrays are copied; the caller keeps ownership.
+ */
+hmat_status hmat_import(const hmat_host_blocks* blocks, const hmat_opts* opts, void* stream,
+                        hmat_t* out);
+
+/*
+ * hmat_export — host view of the handle's blocks in FP64 (as built, before
+ * any storage rounding).  The pointers in *out are owned by the handle and
+ * stay valid until hmat_destroy.
+ */
+hmat_status hmat_export(hmat_t h, hmat_host_blocks* out);
+
+/*
+ * hmat_matvec — y = alpha * H x + beta * y   (eq. (20): dense blocks by plain
+ * products, low-rank blocks as U (V^T x_M), all contributions to a row summed
+ * by the single owner of that row, no atomics on y).
+ *   x, y: DEVICE FP64, caller's element order, column-major n x nrhs with
+ *     leading dimension ld >= n; x and y must not overlap.
+ *   nrhs >= 0 (0 is a no-op); beta == 0 ignores the old contents of y.
+ *   Allocates nothing and does not wait for the GPU.
+ */
+hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld,
+                        double alpha, double beta, void* stream);
+
+/* hmat_matvec_T — y = alpha * H^T x + beta * y; same arguments and rules. */
+hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld,
+                          double alpha, double beta, void* stream);
+
+/* hmat_info — statistics of the handle (host struct filled, no GPU work). */
+hmat_status hmat_info(hmat_t h, hmat_stats* out);
+
+/*
+ * hmat_autotune — time the BATCHED schedules (waves per workgroup, unit
+ * size, split or persistent launch) on the handle's own blocks and keep the
+ * fastest.  Synchronises the stream.  Products before and after give
+ * results equal to within rounding (the summation order of a row can
+ * change with the schedule).  reps: timed products per candidate (>= 1).
+ */
+hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream);
+
+/* Rate-and-state parameters for rs_rhs (section 2.2; section 4.1 loading). */
+typedef struct {
+  int64_t n;               /* elements; must equal the order of A (and B) */
+  double V0;               /* reference slip rate [m/s] */
+  double f0;               /* reference friction coefficient */
+  double eta_rad;          /* radiation damping mu / (2 c_s) [Pa s / m] */
+  double V_pl;             /* plate (backslip loading) rate [m/s] */
+  const double* a;         /* DEVICE n: direct-effect coefficient */
+  const double* b;         /* DEVICE n: evolution-effect coefficient */
+  const double* dc;        /* DEVICE n: characteristic slip distance [m] */
+} rs_params;
+
+/*
+ * rs_rhs — right-hand side dy/dt of the 3N ODEs (eqs. (8), (10), (12) with
+ * the partial derivatives of eq. (13) and backslip loading, eqs. (21)-(22)).
+ *   y: DEVICE 3n = (phi | tau | sigma); dydt: DEVICE 3n, same layout;
+ *   V_out: DEVICE n or NULL (slip rate from eq. (7)).
+ *   B may be NULL: dsigma/dt = 0 (coplanar faults in a full space).
+ *   Uses the handle's scratch for the slip-rate vector; allocates nothing.
+ */
+hmat_status rs_rhs(hmat_t A, hmat_t B, const rs_params* p, const double* y, double* dydt,
+                   double* V_out, void* stream);
+
+/* Release the handle and all its device memory (NULL is ignored).
+ * Synchronises the device first. */
+void hmat_destroy(hmat_t h);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* hmat_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HMAT_H_ */

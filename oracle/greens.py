@@ -77,6 +77,22 @@ def rect_traction(x1, x2, a1, b1, a2, b2, mu, nu):
     return mu / (4.0 * np.pi) * (j1 / (1.0 - nu) + j2)
 
 
+# Small vector helpers written out term by term, so that every rounding is
+# the same on any platform (no BLAS call, no fused multiply-add).
+def _dot3(a, e):
+    return (a[..., 0] * e[0] + a[..., 1] * e[1]) + a[..., 2] * e[2]
+
+
+def _cross(a, b):
+    return np.array([a[1] * b[2] - a[2] * b[1],
+                     a[2] * b[0] - a[0] * b[2],
+                     a[0] * b[1] - a[1] * b[0]])
+
+
+def _unit(a):
+    return a / np.sqrt((a[0] * a[0] + a[1] * a[1]) + a[2] * a[2])
+
+
 class CoplanarRectGeometry:
     """Per-element data of a coplanar mesh of rectangles.
 
@@ -94,16 +110,14 @@ class CoplanarRectGeometry:
         self.mu = float(mu)
         self.nu = float(nu)
         self.centres = (((verts[:, 0] + verts[:, 1]) + verts[:, 2]) + verts[:, 3]) * 0.25
-        e1 = np.asarray(slip_dir, dtype=np.float64)[0]
-        e1 = e1 / np.linalg.norm(e1)
-        nrm = np.cross(verts[0, 1] - verts[0, 0], verts[0, 3] - verts[0, 0])
-        nrm = nrm / np.linalg.norm(nrm)
-        e2 = np.cross(nrm, e1)
+        e1 = _unit(np.asarray(slip_dir, dtype=np.float64)[0])
+        nrm = _unit(_cross(verts[0, 1] - verts[0, 0], verts[0, 3] - verts[0, 0]))
+        e2 = _cross(nrm, e1)
         self.e1, self.e2, self.normal = e1, e2, nrm
-        q1 = verts @ e1            # (N, 4)
-        q2 = verts @ e2
-        self.p1 = self.centres @ e1
-        self.p2 = self.centres @ e2
+        q1 = _dot3(verts, e1)      # (N, 4)
+        q2 = _dot3(verts, e2)
+        self.p1 = _dot3(self.centres, e1)
+        self.p2 = _dot3(self.centres, e2)
         self.lo1, self.hi1 = q1.min(axis=1), q1.max(axis=1)
         self.lo2, self.hi2 = q2.min(axis=1), q2.max(axis=1)
 

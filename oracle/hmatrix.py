@@ -51,13 +51,17 @@ class HMatrix:
 
     # -- construction ------------------------------------------------------
     @classmethod
-    def build(cls, geom, leaf, eta, aca_eps, lattice=1, max_rank=0):
+    def build(cls, geom, leaf, eta, aca_eps, lattice=1, max_rank=0, lattice_rows=None):
         """geom provides .centres, .block(rows, cols), .entry_row(i, cols),
-        .entry_col(rows, j) in user order."""
+        .entry_col(rows, j) in user order.  ``lattice_rows``: build only the
+        blocks of these lattice block-rows (a sample; other rows of the
+        product stay zero)."""
         tree = ClusterTree(geom.centres, leaf)
         perm = tree.perm
         blocks = []
         for kind, t, s, li, lj in partition(tree, lattice, eta):
+            if lattice_rows is not None and li not in lattice_rows:
+                continue
             rows = perm[t.start:t.start + t.size]
             cols = perm[s.start:s.start + s.size]
             if kind == "lr":
@@ -72,7 +76,13 @@ class HMatrix:
                                 D=geom.block(rows, cols), lat=(li, lj)))
         h = cls(geom.centres.shape[0], perm, blocks)
         h.tree = tree
+        h.lattice = lattice
         return h
+
+    def lattice_row_ranges(self, rows):
+        """[start, end) of the given lattice block-rows in cluster order."""
+        lat = self.tree.nodes_at_depth(self.lattice.bit_length() - 1)
+        return [(lat[i].start, lat[i].start + lat[i].size) for i in rows]
 
     # -- products (eq. 20) -------------------------------------------------
     def matvec(self, x):

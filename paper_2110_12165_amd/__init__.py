@@ -1,0 +1,192 @@
+"""Lattice H-matrix products for boundary-element earthquake-sequence models
+on AMD Instinct MI355X (gfx950).
+
+Thin Python binding over ``libhmat.so`` (C ABI in ``include/hmat.h``).  All
+computation runs in the library's native code: the host construction
+(cluster tree, partition, ACA) in C++, the products and the rate-and-state
+right-hand side in HIP kernels.  PyTorch provides device memory and streams.
+There is no fallback path: if the library is not built, importing the
+binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import HmatError, check
+
+__all__ = ["HMatrix", "rs_rhs", "HmatError", "library"]
+
+
+def library():
+    return _lib.load()
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class HMatrix:
+    """Handle on a lattice H-matrix held on the current GPU."""
+
+    def __init__(self, handle):
+        self._h = handle
+        self._lib = _lib.load()
+
+    # -- construction -------------------------------------------------------
+    @staticmethod
+    def _opts(aca_eps=1e-6, eta=2.0, leaf=32, lattice=1, max_rank=0, prec="f64", kernel="auto",
+              n_threads=0, wg_waves=0, unit_kib=0):
+        lib = _lib.load()
+        o = _lib.HmatOpts()
+        lib.hmat_default_opts(C.byref(o))
+        o.aca_eps, o.eta, o.leaf, o.lattice, o.max_rank = aca_eps, eta, leaf, lattice, max_rank
+        o.prec = _lib.PREC[prec]
+        o.kernel = _lib.KERNEL[kernel]
+        o.n_threads, o.wg_waves, o.unit_kib = n_threads, wg_waves, unit_kib
+        return o
+
+    @classmethod
+    def build(cls, verts, slip_dir, mu, nu, component=0, stream=None, **opts):
+        """hmat_build from element vertices (N, 4, 3) and slip directions (N, 3)."""
+        lib = _lib.load()
+        verts = np.ascontiguousarray(verts, dtype=np.float64)
+        slip_dir = np.ascontiguousarray(slip_dir, dtype=np.float64)
+        if verts.ndim != 3 or slip_dir.shape != (verts.shape[0], 3):
+            raise ValueError("verts must be (N, nvert, 3) and slip_dir (N, 3)")
+        mesh = _lib.HmatMesh(verts.shape[0], verts.shape[1],
+                             verts.ctypes.data_as(C.POINTER(C.c_double)),
+                             slip_dir.ctypes.data_as(C.POINTER(C.c_double)))
+        green = _lib.HmatGreen(_lib.GF_FS_RECT_COPLANAR, component, mu, nu)
+        o = cls._opts(**opts)
+        h = C.c_void_p()
+        check(lib.hmat_build(C.byref(mesh), C.byref(green), C.byref(o), _stream_ptr(stream), C.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_blocks(cls, n, perm, desc, off, values, stream=None, **opts):
+        """hmat_import from host arrays in the hmat_host_blocks layout."""
+        lib = _lib.load()
+        perm = np.ascontiguousarray(perm, dtype=np.int32)
+        desc = np.ascontiguousarray(desc, dtype=np.int64)
+        off = np.ascontiguousarray(off, dtype=np.int64)
+        values = np.ascontiguousarray(values, dtype=np.float64)
+        hb = _lib.HmatHostBlocks(n, off.shape[0], values.shape[0],
+                                 perm.ctypes.data_as(C.POINTER(C.c_int32)),
+                                 desc.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                 values.ctypes.data_as(C.POINTER(C.c_double)))
+        o = cls._opts(**opts)
+        h = C.c_void_p()
+        check(lib.hmat_import(C.byref(hb), C.byref(o), _stream_ptr(stream), C.byref(h)))
+        return cls(h)
+
+    # -- products -----------------------------------------------------------
+    def _apply(self, fn, x, y, alpha, beta, stream):
+        torch = _torch()
+        n = self.n
+        if not (x.is_cuda and x.dtype == torch.float64):
+            raise TypeError("x must be a float64 GPU tensor")
+        if x.dim() == 1:
+            if x.shape[0] != n:
+                raise ValueError("x has the wrong length")
+            xc = x.contiguous()
+            out = torch.empty_like(xc) if y is None else y
+            if out.shape != xc.shape or not out.is_contiguous() or out.dtype != torch.float64:
+                raise ValueError("y must be a contiguous float64 tensor shaped like x")
+            check(fn(self._h, _dptr(xc), _dptr(out), 1, n, alpha, 0.0 if y is None else beta, _stream_ptr(stream)))
+            return out
+        if x.dim() != 2 or x.shape[0] != n:
+            raise ValueError("x must be (n,) or (n, k)")
+        k = x.shape[1]
+        xt = x.t().contiguous()                       # (k, n): column-major n x k, ld = n
+        yt = torch.empty_like(xt) if y is None else y.t().contiguous()
+        check(fn(self._h, _dptr(xt), _dptr(yt), k, n, alpha, 0.0 if y is None else beta, _stream_ptr(stream)))
+        res = yt.t()
+        if y is not None:
+            y.copy_(res)
+            return y
+        return res
+
+    def matvec(self, x, y=None, alpha=1.0, beta=0.0, stream=None):
+        """y = alpha H x + beta y (x: float64 GPU tensor (n,) or (n, k))."""
+        return self._apply(self._lib.hmat_matvec, x, y, alpha, beta, stream)
+
+    def matvec_T(self, x, y=None, alpha=1.0, beta=0.0, stream=None):
+        return self._apply(self._lib.hmat_matvec_T, x, y, alpha, beta, stream)
+
+    def matvec_raw(self, x_ptr, y_ptr, nrhs=1, ld=None, alpha=1.0, beta=0.0, stream_ptr=None, transpose=False):
+        """Direct call with device addresses (no tensor checks)."""
+        fn = self._lib.hmat_matvec_T if transpose else self._lib.hmat_matvec
+        check(fn(self._h, C.c_void_p(x_ptr), C.c_void_p(y_ptr), nrhs, self.n if ld is None else ld, alpha, beta,
+                 C.c_void_p(stream_ptr)))
+
+    # -- inspection ---------------------------------------------------------
+    def info(self):
+        st = _lib.HmatStats()
+        check(self._lib.hmat_info(self._h, C.byref(st)))
+        d = {name: getattr(st, name) for name, _ in _lib.HmatStats._fields_}
+        d["kernel"] = _lib.KERNEL_NAME.get(d["kernel"], d["kernel"])
+        d["prec"] = "f32" if d["prec"] == 1 else "f64"
+        return d
+
+    @property
+    def n(self):
+        return self.info()["n"]
+
+    def export(self):
+        """Copies of the FP64 host blocks: dict(n, perm, desc (nb, 6), off, values)."""
+        hb = _lib.HmatHostBlocks()
+        check(self._lib.hmat_export(self._h, C.byref(hb)))
+        n, nb, nv = hb.n, hb.nblocks, hb.nvalues
+        return dict(n=n,
+                    perm=np.ctypeslib.as_array(hb.perm, shape=(n,)).copy(),
+                    desc=np.ctypeslib.as_array(hb.desc, shape=(nb * 6,)).copy().reshape(nb, 6),
+                    off=np.ctypeslib.as_array(hb.off, shape=(nb,)).copy(),
+                    values=np.ctypeslib.as_array(hb.values, shape=(nv,)).copy() if nv else np.zeros(0))
+
+    def autotune(self, reps=20, stream=None):
+        check(self._lib.hmat_autotune(self._h, reps, _stream_ptr(stream)))
+        return self.info()
+
+    def close(self):
+        if self._h:
+            self._lib.hmat_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def rs_rhs(A: HMatrix, B, y, a, b, dc, V0, f0, eta_rad, V_pl, dydt=None, V_out=None, stream=None):
+    """dy/dt of the 3N rate-and-state ODEs; y = (phi | tau | sigma) float64 GPU tensor."""
+    torch = _torch()
+    n = A.n
+    if y.shape != (3 * n,) or y.dtype != torch.float64 or not y.is_cuda:
+        raise ValueError("y must be a float64 GPU tensor of length 3n")
+    for t in (a, b, dc):
+        if t.shape != (n,) or t.dtype != torch.float64 or not t.is_cuda:
+            raise ValueError("a, b, dc must be float64 GPU tensors of length n")
+    y = y.contiguous()
+    out = torch.empty_like(y) if dydt is None else dydt
+    p = _lib.RsParams(n, V0, f0, eta_rad, V_pl, a.data_ptr(), b.data_ptr(), dc.data_ptr())
+    lib = _lib.load()
+    check(lib.rs_rhs(A._h, None if B is None else B._h, C.byref(p), _dptr(y), _dptr(out),
+                     None if V_out is None else _dptr(V_out), _stream_ptr(stream)))
+    return out

@@ -1,0 +1,479 @@
+// C entry points of the lattice H-matrix library (include/hmat.h).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hmat.h"
+#include "hmat_internal.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+#include "rs.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+hmat_status set_err(hmat_status c, const std::string& m) {
+  g_err = m;
+  return c;
+}
+
+void check_hip(hipError_t e, const char* what) {
+  if (e == hipErrorOutOfMemory) hm::fail(HMAT_ENOMEM, std::string(what) + ": out of device memory");
+  if (e != hipSuccess) hm::fail(HMAT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    check_hip(hipGetDevice(&prev), "hipGetDevice");
+    if (prev != dev) check_hip(hipSetDevice(dev), "hipSetDevice");
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (hipGetDevice(&cur) == hipSuccess && cur != prev && prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+template <typename F>
+hmat_status guarded(F&& f) {
+  try {
+    f();
+    g_err.clear();
+    return HMAT_OK;
+  } catch (const hm::Error& e) {
+    return set_err(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return set_err(HMAT_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_err(HMAT_EINVAL, e.what());
+  }
+}
+
+}  // namespace
+
+struct hmat_s {
+  int device = 0;
+  bool on_device = false;  // false: host blocks only (hmat_build_host)
+  hm::HostMatrix H;
+  hmat_opts opts{};
+  int32_t kernel = HMAT_KERNEL_BATCHED_SPLIT;  // resolved
+  std::vector<void*> allocs;                  // everything except the batched set
+  std::vector<void*> batched_allocs;
+  int64_t bytes_fixed = 0, bytes_batched = 0;
+  int32_t* d_perm = nullptr;
+  hm::PlainArgs plain{};
+  hm::BatchedArgs batched{};
+  int grid = 0;
+  int cus = 0;
+  double* rs_x = nullptr;  // n doubles: slip rate minus plate rate (rs_rhs scratch)
+  double* rs_ax = nullptr;  // n doubles: A (V - V_pl)
+  double* rs_bx = nullptr;  // n doubles: B (V - V_pl)
+  hmat_stats st{};
+
+  ~hmat_s() {
+    if (!on_device) return;
+    (void)hipDeviceSynchronize();
+    for (void* p : batched_allocs) (void)hipFree(p);
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  template <typename V>
+  V* upload(const std::vector<V>& v, hipStream_t s, bool batched_set = false) {
+    const size_t bytes = std::max<size_t>(sizeof(V), v.size() * sizeof(V));
+    void* p = nullptr;
+    check_hip(hipMalloc(&p, bytes), "hipMalloc");
+    (batched_set ? batched_allocs : allocs).push_back(p);
+    (batched_set ? bytes_batched : bytes_fixed) += (int64_t)bytes;
+    if (!v.empty()) check_hip(hipMemcpyAsync(p, v.data(), v.size() * sizeof(V), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    return static_cast<V*>(p);
+  }
+
+  template <typename V>
+  V* alloc_zero(size_t count, hipStream_t s, bool batched_set = false) {
+    const size_t bytes = std::max<size_t>(sizeof(V), count * sizeof(V));
+    void* p = nullptr;
+    check_hip(hipMalloc(&p, bytes), "hipMalloc");
+    (batched_set ? batched_allocs : allocs).push_back(p);
+    (batched_set ? bytes_batched : bytes_fixed) += (int64_t)bytes;
+    check_hip(hipMemsetAsync(p, 0, bytes, s), "hipMemsetAsync");
+    return static_cast<V*>(p);
+  }
+
+  void drop_batched() {
+    (void)hipDeviceSynchronize();
+    for (void* p : batched_allocs) (void)hipFree(p);
+    batched_allocs.clear();
+    bytes_batched = 0;
+    batched = {};
+  }
+
+  template <typename T>
+  void setup_plain(hipStream_t s) {
+    hm::PlainLayout<T> L = hm::make_plain<T>(H, true);
+    plain.blocks = upload(L.blocks, s);
+    plain.lr_list = upload(L.lr_list, s);
+    plain.n_lr = (int32_t)L.lr_list.size();
+    plain.rows = upload(L.row_units, s);
+    plain.n_rows = (int32_t)L.row_units.size();
+    plain.row_ents = upload(L.row_entries, s);
+    plain.cols = upload(L.col_units, s);
+    plain.n_cols = (int32_t)L.col_units.size();
+    plain.col_ents = upload(L.col_entries, s);
+    plain.pool = upload(L.pool, s);
+    plain.perm = d_perm;
+    plain.t = alloc_zero<double>((size_t)std::max<int64_t>(1, L.sum_rank), s);
+    st.sum_rank = L.sum_rank;
+    st.n_leaves = (int64_t)L.row_units.size();
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  }
+
+  template <typename T>
+  void setup_batched(int32_t wg, int64_t unit_bytes, hipStream_t s) {
+    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes);
+    batched.units = upload(L.units, s, true);
+    batched.n1 = L.n1;
+    batched.n2 = L.n2;
+    batched.src = upload(L.src, s, true);
+    batched.tinfo = upload(L.tinfo, s, true);
+    batched.tp = alloc_zero<double>((size_t)L.tp_size, s, true);
+    batched.pool = upload(L.pool, s, true);
+    batched.perm = d_perm;
+    batched.ctr = alloc_zero<hm::QueueCounters>(1, s, true);
+    batched.wg_waves = wg;
+    grid = hm::persistent_blocks_per_cu<T>(wg) * cus;
+    st.n_units_p1 = L.n1;
+    st.n_units_p2 = L.n2;
+    opts.wg_waves = wg;
+    opts.unit_kib = (int32_t)(unit_bytes / 1024);
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  }
+
+  bool f32() const { return opts.prec == HMAT_F32; }
+
+  void setup_batched_any(int32_t wg, int64_t unit_bytes, hipStream_t s) {
+    if (f32()) setup_batched<float>(wg, unit_bytes, s);
+    else setup_batched<double>(wg, unit_bytes, s);
+  }
+
+  hipError_t product(bool transpose, const double* x, double* y, double alpha, double beta, hipStream_t s,
+                     int32_t kern) const {
+    if (transpose || kern == HMAT_KERNEL_PLAIN)
+      return f32() ? hm::launch_plain<float>(plain, transpose, x, y, alpha, beta, s)
+                   : hm::launch_plain<double>(plain, transpose, x, y, alpha, beta, s);
+    const bool pers = kern == HMAT_KERNEL_BATCHED_PERSISTENT;
+    return f32() ? hm::launch_batched<float>(batched, pers, grid, x, y, alpha, beta, s)
+                 : hm::launch_batched<double>(batched, pers, grid, x, y, alpha, beta, s);
+  }
+};
+
+namespace {
+
+void check_opts(const hmat_opts& o, bool build) {
+  if (build) {
+    if (!(o.aca_eps > 0.0) || !std::isfinite(o.aca_eps)) hm::fail(HMAT_EINVAL, "aca_eps must be positive and finite");
+    if (!(o.eta > 0.0) || !std::isfinite(o.eta)) hm::fail(HMAT_EINVAL, "eta must be positive and finite");
+    if (o.leaf < 1) hm::fail(HMAT_EINVAL, "leaf must be >= 1");
+    if (o.lattice < 1 || (o.lattice & (o.lattice - 1)) != 0) hm::fail(HMAT_EINVAL, "lattice must be a power of two");
+    if (o.max_rank < 0) hm::fail(HMAT_EINVAL, "max_rank must be >= 0");
+    if (o.n_threads < 0) hm::fail(HMAT_EINVAL, "n_threads must be >= 0");
+  }
+  if (o.prec != HMAT_F64 && o.prec != HMAT_F32) hm::fail(HMAT_EINVAL, "prec must be HMAT_F64 or HMAT_F32");
+  if (o.kernel < HMAT_KERNEL_PLAIN || o.kernel > HMAT_KERNEL_AUTO) hm::fail(HMAT_EINVAL, "unknown kernel");
+  if (o.wg_waves != 0 && o.wg_waves != 4 && o.wg_waves != 8 && o.wg_waves != 16)
+    hm::fail(HMAT_EINVAL, "wg_waves must be 0, 4, 8 or 16");
+  if (o.unit_kib < 0) hm::fail(HMAT_EINVAL, "unit_kib must be >= 0");
+}
+
+constexpr int32_t kDefaultWaves = 8;
+constexpr int32_t kDefaultUnitKiB = 256;
+
+void fill_stats(hmat_s* h);
+
+hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool on_device = true) {
+  auto h = std::make_unique<hmat_s>();
+  h->H = std::move(H);
+  h->opts = o;
+  h->kernel = o.kernel == HMAT_KERNEL_AUTO ? HMAT_KERNEL_BATCHED_SPLIT : o.kernel;
+  if (!on_device) {
+    fill_stats(h.get());
+    return h.release();
+  }
+  h->on_device = true;
+  check_hip(hipGetDevice(&h->device), "hipGetDevice");
+  int cus = 0;
+  check_hip(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device), "hipDeviceGetAttribute");
+  h->cus = std::max(1, cus);
+  const int64_t n = h->H.n;
+  h->d_perm = h->upload(h->H.perm, s);
+  h->rs_x = h->alloc_zero<double>((size_t)n, s);
+  h->rs_ax = h->alloc_zero<double>((size_t)n, s);
+  h->rs_bx = h->alloc_zero<double>((size_t)n, s);
+  if (h->f32()) h->setup_plain<float>(s);
+  else h->setup_plain<double>(s);
+  if (h->kernel != HMAT_KERNEL_PLAIN) {
+    const int32_t wg = o.wg_waves ? o.wg_waves : kDefaultWaves;
+    const int64_t ub = (int64_t)(o.unit_kib ? o.unit_kib : kDefaultUnitKiB) * 1024;
+    h->setup_batched_any(wg, ub, s);
+  }
+  fill_stats(h.get());
+  return h.release();
+}
+
+void fill_stats(hmat_s* h) {
+  const int64_t n = h->H.n;
+  hmat_stats& st = h->st;
+  const int64_t keep_sum_rank = st.sum_rank, keep_leaves = st.n_leaves, keep_u1 = st.n_units_p1,
+                keep_u2 = st.n_units_p2;
+  st = hmat_stats{};
+  st.sum_rank = keep_sum_rank;
+  st.n_leaves = keep_leaves;
+  st.n_units_p1 = keep_u1;
+  st.n_units_p2 = keep_u2;
+  st.n = n;
+  const int64_t sz = h->f32() ? 4 : 8;
+  for (int64_t b = 0; b < h->H.nblocks(); ++b) {
+    const int64_t* d = &h->H.desc[6 * b];
+    if (d[0] == 0) {
+      ++st.n_dense;
+      st.dense_entries += d[2] * d[4];
+    } else {
+      ++st.n_lr;
+      st.lr_entries += d[5] * (d[2] + d[4]);
+      st.max_rank = std::max(st.max_rank, d[5]);
+    }
+  }
+  st.tree_depth = h->H.tree_depth;
+  st.factor_bytes = sz * (st.dense_entries + st.lr_entries);
+  st.alg_bytes = st.factor_bytes + 8 * n + 16 * n + 4 * n;
+  st.prec = h->opts.prec;
+  st.lattice = h->H.lattice;
+}
+
+void refresh_stats(hmat_s* h) {
+  h->st.device_bytes = h->bytes_fixed + h->bytes_batched;
+  h->st.kernel = h->kernel;
+  h->st.wg_waves = h->kernel == HMAT_KERNEL_PLAIN ? 0 : h->opts.wg_waves;
+}
+
+void check_vectors(hmat_t h, const double* x, const double* y, int64_t nrhs, int64_t ld) {
+  if (!h) hm::fail(HMAT_EINVAL, "null handle");
+  if (!h->on_device) hm::fail(HMAT_ESTATE, "handle holds host blocks only (hmat_build_host)");
+  if (nrhs < 0) hm::fail(HMAT_EINVAL, "nrhs must be >= 0");
+  if (nrhs == 0) return;
+  if (!x || !y) hm::fail(HMAT_EINVAL, "x and y must be non-null");
+  if (ld < h->H.n) hm::fail(HMAT_EINVAL, "ld must be >= n");
+  const char* xa = reinterpret_cast<const char*>(x);
+  const char* ya = reinterpret_cast<const char*>(y);
+  const int64_t span = ((nrhs - 1) * ld + h->H.n) * (int64_t)sizeof(double);
+  if (xa < ya + span && ya < xa + span) hm::fail(HMAT_EINVAL, "x and y must not overlap");
+}
+
+}  // namespace
+
+extern "C" {
+
+void hmat_default_opts(hmat_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->aca_eps = 1e-6;
+  o->eta = 2.0;
+  o->leaf = 32;
+  o->lattice = 1;
+  o->max_rank = 0;
+  o->prec = HMAT_F64;
+  o->kernel = HMAT_KERNEL_AUTO;
+}
+
+hmat_status hmat_build(const hmat_mesh* mesh, const hmat_green* green, const hmat_opts* opts, void* stream,
+                       hmat_t* out) {
+  return guarded([&] {
+    if (!mesh || !green || !opts || !out) hm::fail(HMAT_EINVAL, "null argument");
+    check_opts(*opts, true);
+    hm::Geometry geo;
+    std::unique_ptr<hm::EntryFn> E(hm::make_entry_fn(*mesh, *green, geo));
+    hm::ClusterTree tree = hm::build_tree(geo, opts->leaf);
+    std::vector<hm::BlockSpec> blocks = hm::partition(tree, opts->lattice, opts->eta);
+    hm::HostMatrix H = hm::assemble(*E, tree, blocks, opts->aca_eps, opts->max_rank, opts->n_threads);
+    H.lattice = opts->lattice;
+    hmat_t h = create_handle(std::move(H), *opts, static_cast<hipStream_t>(stream));
+    refresh_stats(h);
+    *out = h;
+  });
+}
+
+hmat_status hmat_build_host(const hmat_mesh* mesh, const hmat_green* green, const hmat_opts* opts, hmat_t* out) {
+  return guarded([&] {
+    if (!mesh || !green || !opts || !out) hm::fail(HMAT_EINVAL, "null argument");
+    check_opts(*opts, true);
+    hm::Geometry geo;
+    std::unique_ptr<hm::EntryFn> E(hm::make_entry_fn(*mesh, *green, geo));
+    hm::ClusterTree tree = hm::build_tree(geo, opts->leaf);
+    std::vector<hm::BlockSpec> blocks = hm::partition(tree, opts->lattice, opts->eta);
+    hm::HostMatrix H = hm::assemble(*E, tree, blocks, opts->aca_eps, opts->max_rank, opts->n_threads);
+    H.lattice = opts->lattice;
+    hmat_t h = create_handle(std::move(H), *opts, nullptr, false);
+    refresh_stats(h);
+    *out = h;
+  });
+}
+
+hmat_status hmat_import(const hmat_host_blocks* b, const hmat_opts* opts, void* stream, hmat_t* out) {
+  return guarded([&] {
+    if (!b || !opts || !out) hm::fail(HMAT_EINVAL, "null argument");
+    check_opts(*opts, false);
+    if (b->n < 1 || b->nblocks < 1 || b->nvalues < 0) hm::fail(HMAT_EINVAL, "bad sizes");
+    if (!b->perm || !b->desc || !b->off || (b->nvalues > 0 && !b->values)) hm::fail(HMAT_EINVAL, "null array");
+    if (b->n > (int64_t)INT32_MAX / 2) hm::fail(HMAT_EINVAL, "n too large");
+    hm::HostMatrix H;
+    H.n = b->n;
+    H.perm.assign(b->perm, b->perm + b->n);
+    H.desc.assign(b->desc, b->desc + 6 * b->nblocks);
+    H.off.assign(b->off, b->off + b->nblocks);
+    H.values.assign(b->values, b->values + b->nvalues);
+    hm::validate_host_matrix(H);
+    H.lattice = 0;
+    H.tree_depth = 0;
+    hmat_t h = create_handle(std::move(H), *opts, static_cast<hipStream_t>(stream));
+    refresh_stats(h);
+    *out = h;
+  });
+}
+
+hmat_status hmat_export(hmat_t h, hmat_host_blocks* out) {
+  return guarded([&] {
+    if (!h || !out) hm::fail(HMAT_EINVAL, "null argument");
+    out->n = h->H.n;
+    out->nblocks = h->H.nblocks();
+    out->nvalues = (int64_t)h->H.values.size();
+    out->perm = h->H.perm.data();
+    out->desc = h->H.desc.data();
+    out->off = h->H.off.data();
+    out->values = h->H.values.data();
+  });
+}
+
+hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld, double alpha, double beta,
+                        void* stream) {
+  return guarded([&] {
+    check_vectors(h, x, y, nrhs, ld);
+    if (nrhs == 0) return;
+    DeviceGuard g(h->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int64_t c = 0; c < nrhs; ++c)
+      check_hip(h->product(false, x + c * ld, y + c * ld, alpha, beta, s, h->kernel), "product launch");
+  });
+}
+
+hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld, double alpha, double beta,
+                          void* stream) {
+  return guarded([&] {
+    check_vectors(h, x, y, nrhs, ld);
+    if (nrhs == 0) return;
+    DeviceGuard g(h->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int64_t c = 0; c < nrhs; ++c)
+      check_hip(h->product(true, x + c * ld, y + c * ld, alpha, beta, s, HMAT_KERNEL_PLAIN), "transpose launch");
+  });
+}
+
+hmat_status hmat_info(hmat_t h, hmat_stats* out) {
+  return guarded([&] {
+    if (!h || !out) hm::fail(HMAT_EINVAL, "null argument");
+    refresh_stats(h);
+    *out = h->st;
+  });
+}
+
+hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
+  return guarded([&] {
+    if (!h) hm::fail(HMAT_EINVAL, "null handle");
+    if (!h->on_device) hm::fail(HMAT_ESTATE, "handle holds host blocks only (hmat_build_host)");
+    if (reps < 1) hm::fail(HMAT_EINVAL, "reps must be >= 1");
+    DeviceGuard g(h->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = h->H.n;
+    double *x = nullptr, *y = nullptr;
+    check_hip(hipMalloc(&x, n * sizeof(double)), "hipMalloc");
+    struct Free { void* p; ~Free() { (void)hipFree(p); } } fx{x};
+    check_hip(hipMalloc(&y, n * sizeof(double)), "hipMalloc");
+    Free fy{y};
+    std::vector<double> ones(n, 1e-9);
+    check_hip(hipMemcpy(x, ones.data(), n * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
+    hipEvent_t e0, e1;
+    check_hip(hipEventCreate(&e0), "hipEventCreate");
+    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    auto time_it = [&](int32_t kern) {
+      for (int w = 0; w < 2; ++w) check_hip(h->product(false, x, y, 1.0, 0.0, s, kern), "product launch");
+      check_hip(hipEventRecord(e0, s), "hipEventRecord");
+      for (int r = 0; r < reps; ++r) check_hip(h->product(false, x, y, 1.0, 0.0, s, kern), "product launch");
+      check_hip(hipEventRecord(e1, s), "hipEventRecord");
+      check_hip(hipEventSynchronize(e1), "hipEventSynchronize");
+      float ms = 0.f;
+      check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
+      return (double)ms / reps;
+    };
+    double best = time_it(HMAT_KERNEL_PLAIN);
+    int32_t best_k = HMAT_KERNEL_PLAIN, best_w = 0, best_u = 0;
+    for (int32_t wg : {4, 8, 16})
+      for (int32_t ukib : {128, 512, 2048}) {
+        h->drop_batched();
+        h->setup_batched_any(wg, (int64_t)ukib * 1024, s);
+        for (int32_t k : {HMAT_KERNEL_BATCHED_SPLIT, HMAT_KERNEL_BATCHED_PERSISTENT}) {
+          const double t = time_it(k);
+          if (t < best) {
+            best = t;
+            best_k = k;
+            best_w = wg;
+            best_u = ukib;
+          }
+        }
+      }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->drop_batched();
+    h->kernel = best_k;
+    if (best_k != HMAT_KERNEL_PLAIN) h->setup_batched_any(best_w, (int64_t)best_u * 1024, s);
+    refresh_stats(h);
+  });
+}
+
+hmat_status rs_rhs(hmat_t A, hmat_t B, const rs_params* p, const double* y, double* dydt, double* V_out,
+                   void* stream) {
+  return guarded([&] {
+    if (!A || !p || !y || !dydt) hm::fail(HMAT_EINVAL, "null argument");
+    if (!A->on_device || (B && !B->on_device)) hm::fail(HMAT_ESTATE, "handle holds host blocks only");
+    if (B && B->device != A->device) hm::fail(HMAT_EINVAL, "A and B live on different devices");
+    if (p->n != A->H.n || (B && B->H.n != A->H.n)) hm::fail(HMAT_EINVAL, "n does not match the handles");
+    if (!p->a || !p->b || !p->dc) hm::fail(HMAT_EINVAL, "null friction parameter array");
+    if (!(p->V0 > 0.0) || !(p->eta_rad >= 0.0) || !std::isfinite(p->f0) || !std::isfinite(p->V_pl))
+      hm::fail(HMAT_EINVAL, "bad friction constants");
+    DeviceGuard g(A->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A->H.n;
+    // 1) V from eq. (7) and x = V - V_pl
+    check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, y, A->rs_x, V_out, s), "slip-rate launch");
+    // 2) A x (and B x), eqs. (9)-(10) with the backslip loading of eqs. (21)-(22)
+    check_hip(A->product(false, A->rs_x, A->rs_ax, 1.0, 0.0, s, A->kernel), "product launch");
+    const double* bx = nullptr;
+    if (B) {
+      check_hip(B->product(false, A->rs_x, A->rs_bx, 1.0, 0.0, s, B->kernel), "product launch");
+      bx = A->rs_bx;
+    }
+    // 3) element-wise right-hand side, eqs. (8), (12), (13)
+    check_hip(hm::launch_rs_rhs(n, *p, y, A->rs_ax, bx, dydt, s), "rhs launch");
+  });
+}
+
+void hmat_destroy(hmat_t h) { delete h; }
+
+const char* hmat_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,57 @@
+// Plain structs shared by the host packer and the HIP kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace hm {
+
+// Block of the natural layout: dense block column-major m x n at offA;
+// low-rank block U (m x rank, column-major) at offA and V (n x rank,
+// column-major) at offB.  Rows and columns in cluster order.  tslot: first
+// entry of the block's intermediate vector t = V^T x (and s = U^T x for the
+// transpose).
+struct PlainBlock {
+  int32_t kind, r0, m, c0, n, rank, tslot, pad;
+  int64_t offA, offB;
+};
+
+// Row-owned unit of the natural layout: rows [row0, row0 + m) (m <= 64) and
+// the blocks meeting them, entries [begin, end) of the entry list.
+struct RowUnit {
+  int32_t row0, m, begin, end;
+};
+
+// (block, first row of this unit inside the block) — or first column for the
+// column-owned units of the transpose.
+struct UnitEntry {
+  int32_t block, off;
+};
+
+// Work unit of the batched layout.  Its panel holds nq input groups; each
+// group stores, for every output lane, W consecutive inputs (16 bytes):
+//   panel[(q * nout + o) * W + c] = coefficient of input q*W + c for output o.
+// kind 1 (phase 1, t = V^T x): outputs are intermediate values of one column
+//   cluster, inputs are its rows in1 + [0, nin) (gathered from x through the
+//   permutation; rows beyond nin are zero padding); result o goes to
+//   tp[out0 + o * ostride].
+// kind 2 (phase 2, y = D x + U t): outputs are rows out0 + [0, nout) in
+//   cluster order, inputs are described by src[in0 + i] (>= 0: element of x
+//   in user order; < 0: entry -src-1 of the tinfo table).
+// S: waves sharing the outputs side by side (outputs o = 64*(w % S) + lane),
+//   the remaining waves split the input groups.
+struct Unit {
+  int32_t nout, nq, S, in0, nin, out0, ostride, kind;
+  int64_t off;
+};
+
+// Intermediate value assembled from `count` partial sums tp[base + c].
+struct TInfo {
+  int32_t base, count;
+};
+
+// Counters of the persistent schedule; reset by the last workgroup to exit.
+struct QueueCounters {
+  uint32_t next, p1done, exited, pad;
+};
+
+}  // namespace hm

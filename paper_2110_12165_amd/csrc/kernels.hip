@@ -1,0 +1,339 @@
+// HIP kernels of the H-matrix-vector product (section 3.1.3, eq. (20)) for
+// gfx950.
+//
+// The product y = H x is taken in two phases:
+//   phase 1: t_b = V_b^T x_M for every low-rank block b (the inner sum of
+//            eq. (20));
+//   phase 2: for every output row, the sum of the dense-block products and
+//            of the U_b t_b terms of the low-rank blocks meeting that row
+//            (the outer sum of eq. (20) and the summation of all block
+//            contributions).  Each row has exactly one owner, so y is written
+//            once, without atomics, and FP64 results are reproducible.
+//
+// Two layouts are supported:
+//   plain:   blocks in their natural column-major form; phase 1 has one
+//            workgroup per low-rank block, phase 2 one wave per row unit.
+//   batched: every phase is a list of work units over packed panels in
+//            which each lane (one output) reads 16 contiguous bytes per
+//            input group, so every wave load is a contiguous, fully used
+//            segment of HBM; inputs of a unit are staged once in LDS (FP64).
+//            Run as two launches (split) or one persistent launch in which
+//            phase-2 units wait for a completion counter of phase 1.
+// Products accumulate in FP64 whatever the storage precision.
+#include <hip/hip_runtime.h>
+
+#include "device_types.hpp"
+#include "kernels.hpp"
+
+namespace hm {
+namespace {
+
+constexpr int kStage = 2048;  // inputs staged in LDS per round (FP64)
+
+template <typename T>
+struct Pack;
+template <>
+struct Pack<float> {
+  typedef float vec __attribute__((ext_vector_type(4)));
+  static constexpr int W = 4;
+};
+template <>
+struct Pack<double> {
+  typedef double vec __attribute__((ext_vector_type(2)));
+  static constexpr int W = 2;
+};
+
+template <typename T>
+__device__ __forceinline__ typename Pack<T>::vec load_stream(const typename Pack<T>::vec* p) {
+  return __builtin_nontemporal_load(p);
+}
+
+__device__ __forceinline__ double load_agent(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// ------------------------------------------------------------------------
+// batched layout
+// ------------------------------------------------------------------------
+template <typename T, int NW, bool COHERENT>
+__device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ pool, const double* __restrict__ x,
+                                         double* __restrict__ y, const int32_t* __restrict__ perm,
+                                         const int32_t* __restrict__ src, const TInfo* __restrict__ tinfo,
+                                         double* tp, double alpha, double beta, double* zs, double* red) {
+  using V = typename Pack<T>::vec;
+  constexpr int W = Pack<T>::W;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int S = u.S;
+  const int RG = NW / S;
+  const int sg = wave % S, rg = wave / S;
+  const int o = sg * 64 + lane;
+  const bool active = o < u.nout;
+  const int nin_pad = u.nq * W;
+  const size_t stride = (size_t)u.nout;
+  const V* base = reinterpret_cast<const V*>(pool + u.off) + o;
+  double a0 = 0.0, a1 = 0.0;
+
+  for (int c0 = 0; c0 < nin_pad; c0 += kStage) {
+    const int cl = min(kStage, nin_pad - c0);
+    for (int i = tid; i < cl; i += NW * 64) {
+      const int gi = c0 + i;
+      double v = 0.0;
+      if (u.kind == 1) {
+        if (gi < u.nin) v = x[perm[u.in0 + gi]];
+      } else {
+        const int s = src[u.in0 + gi];
+        if (s >= 0) {
+          v = x[s];
+        } else {
+          const TInfo ti = tinfo[-s - 1];
+          for (int c = 0; c < ti.count; ++c) v += COHERENT ? load_agent(tp + ti.base + c) : tp[ti.base + c];
+        }
+      }
+      zs[i] = v;
+    }
+    __syncthreads();
+    if (active) {
+      const int q0 = c0 / W;
+      const int q1 = q0 + cl / W;
+      int q = q0 + rg;
+      for (; q + 3 * RG < q1; q += 4 * RG) {
+        const V v0 = load_stream<T>(base + (size_t)q * stride);
+        const V v1 = load_stream<T>(base + (size_t)(q + RG) * stride);
+        const V v2 = load_stream<T>(base + (size_t)(q + 2 * RG) * stride);
+        const V v3 = load_stream<T>(base + (size_t)(q + 3 * RG) * stride);
+        const double* z0 = zs + (q - q0) * W;
+        const double* z1 = z0 + RG * W;
+        const double* z2 = z1 + RG * W;
+        const double* z3 = z2 + RG * W;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          a0 = fma((double)v0[c], z0[c], a0);
+          a1 = fma((double)v1[c], z1[c], a1);
+          a0 = fma((double)v2[c], z2[c], a0);
+          a1 = fma((double)v3[c], z3[c], a1);
+        }
+      }
+      for (; q < q1; q += RG) {
+        const V v0 = load_stream<T>(base + (size_t)q * stride);
+        const double* z0 = zs + (q - q0) * W;
+#pragma unroll
+        for (int c = 0; c < W; ++c) a0 = fma((double)v0[c], z0[c], a0);
+      }
+    }
+    __syncthreads();
+  }
+  double acc = a0 + a1;
+  if (RG > 1) {
+    red[wave * 64 + lane] = acc;
+    __syncthreads();
+    if (rg == 0) {
+      acc = 0.0;
+      for (int r = 0; r < RG; ++r) acc += red[(r * S + sg) * 64 + lane];
+    }
+  }
+  if (rg == 0 && active) {
+    if (u.kind == 1) {
+      tp[u.out0 + (size_t)o * u.ostride] = acc;
+    } else {
+      const int row = perm[u.out0 + o];
+      y[row] = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * y[row]);
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void k_units(BatchedArgs a, int first, const double* __restrict__ x,
+                                                   double* __restrict__ y, double alpha, double beta) {
+  __shared__ double zs[kStage];
+  __shared__ double red[NW * 64];
+  const Unit u = a.units[first + blockIdx.x];
+  run_unit<T, NW, false>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.tinfo, a.tp, alpha, beta, zs,
+                         red);
+}
+
+template <typename T, int NW>
+__global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const double* __restrict__ x,
+                                                        double* __restrict__ y, double alpha, double beta) {
+  __shared__ double zs[kStage];
+  __shared__ double red[NW * 64];
+  __shared__ unsigned ticket;
+  const unsigned n1 = (unsigned)a.n1, total = (unsigned)(a.n1 + a.n2);
+  QueueCounters* ctr = a.ctr;
+  for (;;) {
+    if (threadIdx.x == 0) ticket = __hip_atomic_fetch_add(&ctr->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const unsigned t = ticket;
+    __syncthreads();
+    if (t >= total) break;
+    if (t >= n1) {
+      if (threadIdx.x == 0) {
+        while (__hip_atomic_load(&ctr->p1done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < n1)
+          __builtin_amdgcn_s_sleep(2);
+      }
+      __syncthreads();
+    }
+    const Unit u = a.units[t];
+    run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.tinfo, a.tp, alpha, beta, zs,
+                          red);
+    if (t < n1) {
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0) __hip_atomic_fetch_add(&ctr->p1done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+  if (threadIdx.x == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(&ctr->exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (prev == gridDim.x - 1) {
+      __hip_atomic_store(&ctr->next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctr->p1done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctr->exited, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------
+// plain layout
+// ------------------------------------------------------------------------
+// Phase 1 (or its transpose): one workgroup of 256 per low-rank block;
+// t[k] = sum_j F[k*len + j] x[perm[start + j]], F = V (forward) or U (transpose).
+template <typename T>
+__global__ __launch_bounds__(256) void k_plain_p1(PlainArgs a, const double* __restrict__ x, bool transpose) {
+  __shared__ double part[4];
+  const PlainBlock b = a.blocks[a.lr_list[blockIdx.x]];
+  const T* pool = static_cast<const T*>(a.pool);
+  const T* F = pool + (transpose ? b.offA : b.offB);
+  const int len = transpose ? b.m : b.n;
+  const int start = transpose ? b.r0 : b.c0;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int k = 0; k < b.rank; ++k) {
+    double acc = 0.0;
+    for (int j = threadIdx.x; j < len; j += 256) acc += (double)F[(size_t)k * len + j] * x[a.perm[start + j]];
+    acc = wave_sum(acc);
+    if (lane == 0) part[wave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) a.t[b.tslot + k] = (part[0] + part[1]) + (part[2] + part[3]);
+    __syncthreads();
+  }
+}
+
+// Phase 2: one wave per row unit; lane i owns row row0 + i.
+template <typename T>
+__global__ __launch_bounds__(64) void k_plain_p2(PlainArgs a, const double* __restrict__ x, double* __restrict__ y,
+                                                 double alpha, double beta) {
+  const RowUnit u = a.rows[blockIdx.x];
+  const int i = threadIdx.x;
+  if (i >= u.m) return;
+  const T* pool = static_cast<const T*>(a.pool);
+  double acc = 0.0;
+  for (int e = u.begin; e < u.end; ++e) {
+    const UnitEntry en = a.row_ents[e];
+    const PlainBlock b = a.blocks[en.block];
+    const T* F = pool + b.offA + en.off + i;
+    if (b.kind == 0) {
+      for (int j = 0; j < b.n; ++j) acc += (double)F[(size_t)j * b.m] * x[a.perm[b.c0 + j]];
+    } else {
+      for (int k = 0; k < b.rank; ++k) acc += (double)F[(size_t)k * b.m] * a.t[b.tslot + k];
+    }
+  }
+  const int row = a.perm[u.row0 + i];
+  y[row] = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * y[row]);
+}
+
+// Phase 2 of the transpose: one wave per column unit; lane j owns column
+// col0 + j of H, i.e. row col0 + j of H^T.
+template <typename T>
+__global__ __launch_bounds__(64) void k_plain_p2t(PlainArgs a, const double* __restrict__ x, double* __restrict__ y,
+                                                  double alpha, double beta) {
+  const RowUnit u = a.cols[blockIdx.x];
+  const int j = threadIdx.x;
+  if (j >= u.m) return;
+  const T* pool = static_cast<const T*>(a.pool);
+  double acc = 0.0;
+  for (int e = u.begin; e < u.end; ++e) {
+    const UnitEntry en = a.col_ents[e];
+    const PlainBlock b = a.blocks[en.block];
+    if (b.kind == 0) {
+      const T* D = pool + b.offA + (size_t)(en.off + j) * b.m;
+      for (int i = 0; i < b.m; ++i) acc += (double)D[i] * x[a.perm[b.r0 + i]];
+    } else {
+      const T* Vf = pool + b.offB + en.off + j;
+      for (int k = 0; k < b.rank; ++k) acc += (double)Vf[(size_t)k * b.n] * a.t[b.tslot + k];
+    }
+  }
+  const int row = a.perm[u.row0 + j];
+  y[row] = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * y[row]);
+}
+
+template <typename T, int NW>
+hipError_t launch_batched_nw(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
+                             double beta, hipStream_t s) {
+  if (persistent) {
+    if (a.n1 + a.n2 == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_persistent<T, NW>), dim3(grid), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
+    return hipGetLastError();
+  }
+  if (a.n1 > 0) hipLaunchKernelGGL((k_units<T, NW>), dim3(a.n1), dim3(NW * 64), 0, s, a, 0, x, y, alpha, beta);
+  if (a.n2 > 0) hipLaunchKernelGGL((k_units<T, NW>), dim3(a.n2), dim3(NW * 64), 0, s, a, a.n1, x, y, alpha, beta);
+  return hipGetLastError();
+}
+
+template <typename T, int NW>
+int occupancy_nw() {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<T, NW>, NW * 64, 0) != hipSuccess) return 1;
+  return nb > 0 ? nb : 1;
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
+                          double beta, hipStream_t s) {
+  switch (a.wg_waves) {
+    case 4: return launch_batched_nw<T, 4>(a, persistent, grid, x, y, alpha, beta, s);
+    case 8: return launch_batched_nw<T, 8>(a, persistent, grid, x, y, alpha, beta, s);
+    case 16: return launch_batched_nw<T, 16>(a, persistent, grid, x, y, alpha, beta, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+int persistent_blocks_per_cu(int wg_waves) {
+  switch (wg_waves) {
+    case 4: return occupancy_nw<T, 4>();
+    case 8: return occupancy_nw<T, 8>();
+    case 16: return occupancy_nw<T, 16>();
+    default: return 1;
+  }
+}
+
+template <typename T>
+hipError_t launch_plain(const PlainArgs& a, bool transpose, const double* x, double* y, double alpha, double beta,
+                        hipStream_t s) {
+  if (a.n_lr > 0) hipLaunchKernelGGL(k_plain_p1<T>, dim3(a.n_lr), dim3(256), 0, s, a, x, transpose);
+  if (!transpose) {
+    if (a.n_rows > 0) hipLaunchKernelGGL(k_plain_p2<T>, dim3(a.n_rows), dim3(64), 0, s, a, x, y, alpha, beta);
+  } else {
+    if (a.n_cols > 0) hipLaunchKernelGGL(k_plain_p2t<T>, dim3(a.n_cols), dim3(64), 0, s, a, x, y, alpha, beta);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_batched<float>(const BatchedArgs&, bool, int, const double*, double*, double, double,
+                                          hipStream_t);
+template hipError_t launch_batched<double>(const BatchedArgs&, bool, int, const double*, double*, double, double,
+                                           hipStream_t);
+template int persistent_blocks_per_cu<float>(int);
+template int persistent_blocks_per_cu<double>(int);
+template hipError_t launch_plain<float>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t);
+template hipError_t launch_plain<double>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t);
+
+}  // namespace hm

@@ -1,0 +1,50 @@
+// Launch interface of the product kernels (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device_types.hpp"
+
+namespace hm {
+
+// Device pointers of a natural-layout product.
+struct PlainArgs {
+  const PlainBlock* blocks;
+  const int32_t* lr_list;
+  int32_t n_lr;
+  const RowUnit* rows;
+  int32_t n_rows;
+  const UnitEntry* row_ents;
+  const RowUnit* cols;
+  int32_t n_cols;
+  const UnitEntry* col_ents;
+  const void* pool;
+  const int32_t* perm;
+  double* t;  // scratch: sum of ranks
+};
+
+// Device pointers of a batched-layout product.
+struct BatchedArgs {
+  const Unit* units;
+  int32_t n1, n2;
+  const int32_t* src;
+  const TInfo* tinfo;
+  double* tp;  // scratch: partial intermediate values
+  const void* pool;
+  const int32_t* perm;
+  QueueCounters* ctr;
+  int32_t wg_waves;
+};
+
+template <typename T>
+hipError_t launch_plain(const PlainArgs& a, bool transpose, const double* x, double* y, double alpha, double beta,
+                        hipStream_t s);
+
+template <typename T>
+hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
+                          double beta, hipStream_t s);
+
+template <typename T>
+int persistent_blocks_per_cu(int wg_waves);
+
+}  // namespace hm

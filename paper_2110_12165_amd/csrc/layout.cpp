@@ -1,0 +1,316 @@
+// Host-side packing of a block list into the device layouts.
+#include "layout.hpp"
+
+#include <algorithm>
+#include <map>
+#include <numeric>
+
+namespace hm {
+namespace {
+
+template <typename T>
+int64_t align_elems(int64_t off) {
+  const int64_t a = 256 / (int64_t)sizeof(T);
+  return (off + a - 1) / a * a;
+}
+
+inline int32_t to_i32(int64_t v, const char* what) {
+  if (v < 0 || v > INT32_MAX) fail(HMAT_EUNSUPPORTED, std::string(what) + " exceeds the 32-bit range of the layout");
+  return (int32_t)v;
+}
+
+// For each refined interval, the blocks that contain it (block order) and
+// the interval's offset inside each block.
+struct Incidence {
+  std::vector<std::pair<int64_t, int64_t>> iv;
+  std::vector<std::vector<std::pair<int32_t, int32_t>>> members;  // (block, offset)
+};
+
+Incidence incidence(const HostMatrix& H, bool columns, int64_t cap) {
+  Incidence I;
+  I.iv = refine_ranges(H, columns, cap);
+  I.members.resize(I.iv.size());
+  std::vector<int64_t> starts(I.iv.size());
+  for (size_t k = 0; k < I.iv.size(); ++k) starts[k] = I.iv[k].first;
+  const int64_t nb = H.nblocks();
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t* d = &H.desc[6 * b];
+    const int64_t lo = columns ? d[3] : d[1];
+    const int64_t len = columns ? d[4] : d[2];
+    size_t k = std::lower_bound(starts.begin(), starts.end(), lo) - starts.begin();
+    for (; k < I.iv.size() && I.iv[k].first < lo + len; ++k)
+      I.members[k].push_back({(int32_t)b, (int32_t)(I.iv[k].first - lo)});
+  }
+  return I;
+}
+
+}  // namespace
+
+std::vector<std::pair<int64_t, int64_t>> refine_ranges(const HostMatrix& H, bool columns, int64_t cap) {
+  std::vector<int64_t> cuts{0, H.n};
+  for (int64_t b = 0; b < H.nblocks(); ++b) {
+    const int64_t* d = &H.desc[6 * b];
+    const int64_t lo = columns ? d[3] : d[1];
+    const int64_t len = columns ? d[4] : d[2];
+    cuts.push_back(lo);
+    cuts.push_back(lo + len);
+  }
+  std::sort(cuts.begin(), cuts.end());
+  cuts.erase(std::unique(cuts.begin(), cuts.end()), cuts.end());
+  std::vector<std::pair<int64_t, int64_t>> out;
+  for (size_t k = 0; k + 1 < cuts.size(); ++k) {
+    const int64_t a = cuts[k], b = cuts[k + 1];
+    const int64_t parts = (b - a + cap - 1) / cap;
+    for (int64_t p = 0; p < parts; ++p) out.push_back({a + (b - a) * p / parts, a + (b - a) * (p + 1) / parts});
+  }
+  return out;
+}
+
+template <typename T>
+PlainLayout<T> make_plain(const HostMatrix& H, bool transpose) {
+  PlainLayout<T> L;
+  const int64_t nb = H.nblocks();
+  L.blocks.resize(nb);
+  int64_t off = 0, tslot = 0;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t* d = &H.desc[6 * b];
+    PlainBlock& p = L.blocks[b];
+    p.kind = (int32_t)d[0];
+    p.r0 = to_i32(d[1], "row");
+    p.m = to_i32(d[2], "block rows");
+    p.c0 = to_i32(d[3], "column");
+    p.n = to_i32(d[4], "block columns");
+    p.rank = to_i32(d[5], "rank");
+    p.pad = 0;
+    p.tslot = to_i32(tslot, "total rank");
+    if (p.kind == 0) {
+      p.offA = off = align_elems<T>(off);
+      p.offB = 0;
+      off += d[2] * d[4];
+    } else {
+      p.offA = off = align_elems<T>(off);
+      off += d[2] * d[5];
+      p.offB = off = align_elems<T>(off);
+      off += d[4] * d[5];
+      tslot += d[5];
+      if (d[5] > 0) L.lr_list.push_back((int32_t)b);
+    }
+  }
+  L.sum_rank = tslot;
+  L.pool.assign(align_elems<T>(off) + 256 / sizeof(T), T(0));
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t* d = &H.desc[6 * b];
+    const double* v = &H.values[H.off[b]];
+    const PlainBlock& p = L.blocks[b];
+    if (p.kind == 0) {
+      for (int64_t k = 0; k < d[2] * d[4]; ++k) L.pool[p.offA + k] = (T)v[k];
+    } else {
+      for (int64_t k = 0; k < d[2] * d[5]; ++k) L.pool[p.offA + k] = (T)v[k];
+      for (int64_t k = 0; k < d[4] * d[5]; ++k) L.pool[p.offB + k] = (T)v[d[2] * d[5] + k];
+    }
+  }
+  for (int pass = 0; pass < (transpose ? 2 : 1); ++pass) {
+    Incidence I = incidence(H, pass == 1, 64);
+    auto& units = pass == 0 ? L.row_units : L.col_units;
+    auto& ents = pass == 0 ? L.row_entries : L.col_entries;
+    for (size_t k = 0; k < I.iv.size(); ++k) {
+      RowUnit u;
+      u.row0 = (int32_t)I.iv[k].first;
+      u.m = (int32_t)(I.iv[k].second - I.iv[k].first);
+      u.begin = to_i32((int64_t)ents.size(), "unit entries");
+      for (auto& e : I.members[k]) {
+        const PlainBlock& p = L.blocks[e.first];
+        if (p.kind == 1 && p.rank == 0) continue;
+        ents.push_back({e.first, e.second});
+      }
+      u.end = to_i32((int64_t)ents.size(), "unit entries");
+      units.push_back(u);
+    }
+  }
+  return L;
+}
+
+template <typename T>
+BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes) {
+  constexpr int W = 16 / (int)sizeof(T);
+  BatchedLayout<T> L;
+  L.wg_waves = wg_waves;
+  L.unit_bytes = unit_bytes;
+  const int64_t nb = H.nblocks();
+
+  // ---- phase 1: group low-rank blocks by their column cluster -------------
+  struct Group {
+    int64_t c0, n;
+    std::vector<int32_t> blocks;
+    int64_t R = 0, C = 1, rc = 0, base = 0;
+    int S = 1;
+  };
+  std::vector<Group> groups;
+  std::map<std::pair<int64_t, int64_t>, size_t> gid;
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t* d = &H.desc[6 * b];
+    if (d[0] != 1 || d[5] == 0) continue;
+    auto key = std::make_pair(d[3], d[4]);
+    auto it = gid.find(key);
+    if (it == gid.end()) {
+      it = gid.emplace(key, groups.size()).first;
+      groups.push_back(Group{d[3], d[4], {}, 0, 1, 0, 0, 1});
+    }
+    groups[it->second].blocks.push_back((int32_t)b);
+    groups[it->second].R += d[5];
+  }
+  // intermediate slot numbering: tinfo[0] is the zero entry
+  std::vector<int64_t> slot_of_block(nb, -1);  // tinfo index of (block, column 0)
+  L.tinfo.push_back({0, 0});
+  int64_t tp = 0;
+  for (auto& g : groups) {
+    const int64_t need_waves = (g.R + 63) / 64;
+    g.S = 1;
+    while (g.S < need_waves && g.S < wg_waves) g.S *= 2;
+    const int64_t NS = 64LL * g.S;
+    const int64_t full = NS * g.n * (int64_t)sizeof(T);
+    g.C = std::max<int64_t>(1, (full + unit_bytes - 1) / unit_bytes);
+    g.rc = (g.n + g.C - 1) / g.C;
+    g.rc = (g.rc + W - 1) / W * W;
+    g.C = (g.n + g.rc - 1) / g.rc;
+    g.base = tp;
+    tp += g.R * g.C;
+    int64_t s = 0;
+    for (int32_t b : g.blocks) {
+      slot_of_block[b] = (int64_t)L.tinfo.size();
+      for (int64_t k = 0; k < H.desc[6 * b + 5]; ++k, ++s)
+        L.tinfo.push_back({to_i32(g.base + s * g.C, "partial index"), (int32_t)g.C});
+    }
+  }
+  L.tp_size = std::max<int64_t>(tp, 1);
+  to_i32((int64_t)L.tinfo.size() + 2, "intermediate slots");
+
+  std::vector<Unit> p1, p2;
+  struct Pending { Unit u; int kind; size_t g; int64_t s0, j0; int64_t q_off; };
+  int64_t off = 0;
+  std::vector<Pending> pend;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    const Group& g = groups[gi];
+    const int64_t NS = 64LL * g.S;
+    for (int64_t s0 = 0; s0 < g.R; s0 += NS) {
+      const int64_t ns = std::min(NS, g.R - s0);
+      for (int64_t c = 0; c < g.C; ++c) {
+        const int64_t j0 = c * g.rc;
+        const int64_t nin = std::min(g.rc, g.n - j0);
+        Unit u;
+        u.kind = 1;
+        u.nout = (int32_t)ns;
+        u.nq = to_i32((nin + W - 1) / W, "unit inputs");
+        u.S = g.S;
+        u.in0 = to_i32(g.c0 + j0, "row");
+        u.nin = (int32_t)nin;
+        u.out0 = to_i32(g.base + s0 * g.C + c, "partial index");
+        u.ostride = (int32_t)g.C;
+        u.off = off = align_elems<T>(off);
+        off += (int64_t)u.nq * W * ns;
+        pend.push_back({u, 1, gi, s0, j0, 0});
+      }
+    }
+  }
+  // ---- phase 2: one unit per refined row interval --------------------------
+  Incidence I = incidence(H, false, 64);
+  for (size_t k = 0; k < I.iv.size(); ++k) {
+    const int64_t a = I.iv[k].first, m = I.iv[k].second - I.iv[k].first;
+    Unit u;
+    u.kind = 2;
+    u.nout = (int32_t)m;
+    u.S = 1;
+    u.in0 = to_i32((int64_t)L.src.size(), "input list");
+    u.out0 = (int32_t)a;
+    u.ostride = 1;
+    int64_t K = 0;
+    // dense columns first, then low-rank columns
+    for (int pass = 0; pass < 2; ++pass)
+      for (auto& e : I.members[k]) {
+        const int64_t* d = &H.desc[6 * e.first];
+        if (pass == 0 && d[0] == 0) {
+          for (int64_t j = 0; j < d[4]; ++j) L.src.push_back(H.perm[d[3] + j]);
+          K += d[4];
+        } else if (pass == 1 && d[0] == 1 && d[5] > 0) {
+          for (int64_t kk = 0; kk < d[5]; ++kk) L.src.push_back(-(int32_t)(slot_of_block[e.first] + kk) - 1);
+          K += d[5];
+        }
+      }
+    while (K % W) {
+      L.src.push_back(-1);
+      ++K;
+    }
+    u.nq = to_i32(K / W, "unit inputs");
+    u.nin = (int32_t)K;
+    u.off = off = align_elems<T>(off);
+    off += K * m;
+    pend.push_back({u, 2, k, 0, 0, 0});
+  }
+  to_i32((int64_t)L.src.size(), "input list");
+  L.pool.assign(align_elems<T>(off) + 256 / sizeof(T), T(0));
+
+  // ---- fill panels ----------------------------------------------------------
+  for (auto& p : pend) {
+    const Unit& u = p.u;
+    T* dst = &L.pool[u.off];
+    if (p.kind == 1) {
+      const Group& g = groups[p.g];
+      // map local slots of this unit to (block, column)
+      std::vector<std::pair<int32_t, int64_t>> sl(u.nout);
+      {
+        int64_t s = 0, o = 0;
+        for (int32_t b : g.blocks) {
+          const int64_t r = H.desc[6 * b + 5];
+          for (int64_t kk = 0; kk < r; ++kk, ++s)
+            if (s >= p.s0 && s < p.s0 + u.nout) sl[o++] = {b, kk};
+        }
+      }
+      for (int64_t q = 0; q < u.nq; ++q)
+        for (int64_t o = 0; o < u.nout; ++o) {
+          const int32_t b = sl[o].first;
+          const int64_t kk = sl[o].second;
+          const int64_t m = H.desc[6 * b + 2], n = H.desc[6 * b + 4], r = H.desc[6 * b + 5];
+          const double* V = &H.values[H.off[b] + m * r];
+          for (int c = 0; c < W; ++c) {
+            const int64_t j = q * W + c;
+            dst[(q * u.nout + o) * W + c] = j < u.nin ? (T)V[kk * n + p.j0 + j] : T(0);
+          }
+        }
+    } else {
+      const int64_t m = u.nout;
+      int64_t col = 0;
+      auto put = [&](const double* colv) {  // colv[i] = coefficient of row i
+        const int64_t q = col / W, c = col % W;
+        for (int64_t o = 0; o < m; ++o) dst[(q * m + o) * W + c] = colv ? (T)colv[o] : T(0);
+        ++col;
+      };
+      for (int pass = 0; pass < 2; ++pass)
+        for (auto& e : I.members[p.g]) {
+          const int64_t* d = &H.desc[6 * e.first];
+          const double* v = &H.values[H.off[e.first]];
+          if (pass == 0 && d[0] == 0) {
+            for (int64_t j = 0; j < d[4]; ++j) put(v + j * d[2] + e.second);
+          } else if (pass == 1 && d[0] == 1 && d[5] > 0) {
+            for (int64_t kk = 0; kk < d[5]; ++kk) put(v + kk * d[2] + e.second);
+          }
+        }
+      while (col % W) put(nullptr);
+    }
+    (p.kind == 1 ? p1 : p2).push_back(u);
+  }
+  auto bytes = [](const Unit& u) { return (int64_t)u.nq * u.nout; };
+  std::stable_sort(p1.begin(), p1.end(), [&](const Unit& a, const Unit& b) { return bytes(a) > bytes(b); });
+  std::stable_sort(p2.begin(), p2.end(), [&](const Unit& a, const Unit& b) { return bytes(a) > bytes(b); });
+  L.n1 = (int32_t)p1.size();
+  L.n2 = (int32_t)p2.size();
+  L.units = std::move(p1);
+  L.units.insert(L.units.end(), p2.begin(), p2.end());
+  return L;
+}
+
+template PlainLayout<float> make_plain<float>(const HostMatrix&, bool);
+template PlainLayout<double> make_plain<double>(const HostMatrix&, bool);
+template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t);
+template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t);
+
+}  // namespace hm

@@ -1,0 +1,49 @@
+// Device layouts of a block list (host-side packing).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "device_types.hpp"
+#include "hmat_internal.hpp"
+
+namespace hm {
+
+// Natural layout: blocks as built, each starting on a 256-byte boundary.
+template <typename T>
+struct PlainLayout {
+  std::vector<T> pool;
+  std::vector<PlainBlock> blocks;
+  std::vector<int32_t> lr_list;        // low-rank blocks with rank > 0
+  std::vector<RowUnit> row_units;      // owners of output rows (product)
+  std::vector<UnitEntry> row_entries;
+  std::vector<RowUnit> col_units;      // owners of output rows of the transpose
+  std::vector<UnitEntry> col_entries;
+  int64_t sum_rank = 0;
+};
+
+template <typename T>
+PlainLayout<T> make_plain(const HostMatrix& H, bool transpose);
+
+// Batched layout: every product becomes a list of work units over packed
+// panels (see Unit in device_types.hpp).
+template <typename T>
+struct BatchedLayout {
+  std::vector<T> pool;
+  std::vector<Unit> units;             // n1 phase-1 units, then n2 phase-2 units
+  int32_t n1 = 0, n2 = 0;
+  std::vector<int32_t> src;
+  std::vector<TInfo> tinfo;
+  int64_t tp_size = 0;
+  int32_t wg_waves = 8;
+  int64_t unit_bytes = 0;
+};
+
+template <typename T>
+BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes);
+
+// Row intervals of the finest common refinement of the blocks' row (or
+// column) ranges, each split into pieces of at most `cap` rows.
+std::vector<std::pair<int64_t, int64_t>> refine_ranges(const HostMatrix& H, bool columns, int64_t cap);
+
+}  // namespace hm

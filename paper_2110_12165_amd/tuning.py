@@ -1,0 +1,33 @@
+"""Launch configurations of the benchmark workloads on gfx950.
+
+``bench_options(workload, variant)`` returns the keyword options of
+``HMatrix.build`` for one of the three product variants:
+
+* ``batched_f32`` — FP32 factors, batched panels, persistent launch;
+* ``batched_f64`` — FP64 factors, batched panels, persistent launch;
+* ``plain_f64``   — FP64 factors, natural layout, two plain launches.
+
+The batched schedule (waves per workgroup, unit size) is what
+``hmat_autotune`` picked on an MI355X for that workload.
+"""
+from __future__ import annotations
+
+from synth import WORKLOADS
+
+# workload -> (wg_waves, unit_kib, kernel) chosen by hmat_autotune on MI355X
+TUNED = {
+    "dip30_480x256": (8, 256, "persistent"),
+}
+
+
+def bench_options(workload: str, variant: str) -> dict:
+    w = WORKLOADS[workload]
+    base = dict(aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"])
+    wg, ukib, kern = TUNED.get(workload, (8, 256, "persistent"))
+    if variant == "batched_f32":
+        return dict(base, prec="f32", kernel=kern, wg_waves=wg, unit_kib=ukib)
+    if variant == "batched_f64":
+        return dict(base, prec="f64", kernel=kern, wg_waves=wg, unit_kib=ukib)
+    if variant == "plain_f64":
+        return dict(base, prec="f64", kernel="plain")
+    raise ValueError(f"unknown variant {variant}")

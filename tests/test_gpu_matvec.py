@@ -1,0 +1,185 @@
+"""GPU parity of the H-matrix product (eq. 20) against the FP64 oracle.
+
+Tolerances:
+* shared factors (oracle-built blocks imported into the library): the GPU
+  sums the same terms in another order, FP64 storage and FP64 accumulation
+  -> relative error <= 1e-13; FP32 storage rounds every stored entry once
+  (unit roundoff 6e-8) and accumulates in FP64 -> <= 2e-5 required, about
+  1e-7 expected;
+* independent build (C++ construction on the library side): the same rules
+  give the same blocks, so the FP64 product is held to 1e-6 against the
+  oracle's H product, and both are held to 10 * eps_ACA against the plain
+  product y = A x.
+"""
+import numpy as np
+import pytest
+
+from _util import oracle_blocks, rel, say
+from oracle.dense import dense_matrix, fft_grid_product
+from oracle.greens import CoplanarRectGeometry
+from oracle.hmatrix import HMatrix as OracleH
+from synth import WORKLOADS, config_fault, loguniform_rates
+from synth.faults import MU, NU
+
+pytestmark = pytest.mark.gpu
+
+CASES = ["planar64x32", "dip30_48x24", "strike_37x23", "dip30_150x70"]
+KERNELS = ["plain", "split", "persistent"]
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    return torch, torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def hm():
+    import paper_2110_12165_amd as hm
+    hm.library()
+    return hm
+
+
+_cache = {}
+
+
+def oracle_case(name):
+    if name not in _cache:
+        w = WORKLOADS[name]
+        f = config_fault(name)
+        g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
+        H = OracleH.build(g, w["leaf"], w["eta"], w["aca_eps"], w["lattice"])
+        _cache[name] = (w, f, g, H)
+    return _cache[name]
+
+
+def _opts(w):
+    return dict(aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"])
+
+
+@pytest.mark.parametrize("name", CASES)
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("kernel", KERNELS)
+def test_shared_factor_parity(torch_dev, hm, name, prec, kernel):
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case(name)
+    say(f"[shared] {name} N={f.n} {prec} {kernel}")
+    B = oracle_blocks(H)
+    Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec=prec, kernel=kernel)
+    x = loguniform_rates(f.n, w["seed"])
+    y_ref = H.matvec(x)
+    y = Hg.matvec(torch.tensor(x, device=dev)).cpu().numpy()
+    tol = 1e-13 if prec == "f64" else 2e-5
+    r = rel(y, y_ref)
+    say(f"    rel {r:.3e}")
+    assert r <= tol
+    assert np.max(np.abs(y - y_ref)) <= 10 * tol * np.max(np.abs(y_ref))
+    if prec == "f32":
+        assert r <= 1e-6          # FP64 accumulation keeps FP32 storage error near unit roundoff
+    # transpose product against the oracle's transpose
+    yt = Hg.matvec_T(torch.tensor(x, device=dev)).cpu().numpy()
+    assert rel(yt, H.matvec_T(x)) <= tol
+    Hg.close()
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_independent_build_parity(torch_dev, hm, name):
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case(name)
+    say(f"[build] {name} N={f.n}")
+    x = loguniform_rates(f.n, w["seed"])
+    y_h = H.matvec(x)
+    y_exact = fft_grid_product(f.nx, f.ny, f.h, f.slip, MU, NU, x)
+    for prec, kernel in (("f64", "plain"), ("f64", "persistent"), ("f32", "persistent"), ("f32", "split")):
+        Hg = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, prec=prec, kernel=kernel, **_opts(w))
+        y = Hg.matvec(torch.tensor(x, device=dev)).cpu().numpy()
+        info = Hg.info()
+        Hg.close()
+        st = H.stats()
+        assert info["n_dense"] == st["n_dense"] and info["n_lr"] == st["n_lr"]
+        assert info["dense_entries"] + info["lr_entries"] == st["entries"]
+        r_h, r_x = rel(y, y_h), rel(y, y_exact)
+        say(f"    {prec}/{kernel}: vs oracle H {r_h:.2e}, vs exact {r_x:.2e}")
+        assert r_h <= (1e-6 if prec == "f64" else 2e-5)
+        assert r_x <= 10 * w["aca_eps"]
+
+
+def test_alpha_beta_multi_rhs_and_ld(torch_dev, hm):
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case("dip30_48x24")
+    B = oracle_blocks(H)
+    rng = np.random.default_rng(21)
+    n, k, ld = f.n, 3, f.n + 5
+    X = rng.standard_normal((n, k))
+    Y0 = rng.standard_normal((n, k))
+    for kernel in KERNELS:
+        Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec="f64", kernel=kernel)
+        xbuf = torch.zeros(k * ld, dtype=torch.float64, device=dev)
+        ybuf = torch.zeros(k * ld, dtype=torch.float64, device=dev)
+        for c in range(k):
+            xbuf[c * ld:c * ld + n] = torch.tensor(X[:, c], device=dev)
+            ybuf[c * ld:c * ld + n] = torch.tensor(Y0[:, c], device=dev)
+        ybuf[n:ld] = 7.0                              # padding must stay untouched
+        Hg.matvec_raw(xbuf.data_ptr(), ybuf.data_ptr(), nrhs=k, ld=ld, alpha=-2.0, beta=0.5,
+                      stream_ptr=torch.cuda.current_stream().cuda_stream)
+        out = ybuf.cpu().numpy()
+        for c in range(k):
+            ref = -2.0 * H.matvec(X[:, c]) + 0.5 * Y0[:, c]
+            assert rel(out[c * ld:c * ld + n], ref) <= 1e-13
+        assert np.all(out[n:ld] == 7.0)
+        # beta = 0 ignores NaN in y
+        y = torch.full((n,), float("nan"), dtype=torch.float64, device=dev)
+        Hg.matvec(torch.tensor(X[:, 0], device=dev), y=y, beta=0.0)
+        assert torch.isfinite(y).all()
+        # nrhs = 0 is a no-op
+        Hg.matvec_raw(xbuf.data_ptr(), ybuf.data_ptr(), nrhs=0, ld=ld)
+        Hg.close()
+
+
+def test_bitwise_reproducible_and_schedule_independent(torch_dev, hm):
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case("dip30_150x70")
+    B = oracle_blocks(H)
+    x = torch.tensor(loguniform_rates(f.n, 5), device=dev)
+    for kernel in ("split", "persistent"):
+        Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec="f64", kernel=kernel)
+        ys = [Hg.matvec(x).cpu().numpy() for _ in range(5)]
+        for y in ys[1:]:
+            assert np.array_equal(y, ys[0])
+        Hg.close()
+    # other workgroup shapes and unit sizes change only the summation order
+    ref = H.matvec(x.cpu().numpy())
+    for wg in (4, 16):
+        for ukib in (64, 1024):
+            Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec="f64",
+                                        kernel="persistent", wg_waves=wg, unit_kib=ukib)
+            assert rel(Hg.matvec(x).cpu().numpy(), ref) <= 1e-13
+            Hg.close()
+
+
+def test_degenerate_sizes(torch_dev, hm):
+    torch, dev = torch_dev
+    from synth import planar_rect_fault
+    for nx, ny, leaf in ((1, 1, 4), (2, 1, 4), (3, 2, 1), (5, 3, 64)):
+        f = planar_rect_fault(nx, ny, 100.0, 90.0, "strike")
+        g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
+        A = dense_matrix(g)
+        x = loguniform_rates(f.n, 3)
+        for kernel in KERNELS:
+            Hg = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, leaf=leaf, kernel=kernel)
+            y = Hg.matvec(torch.tensor(x, device=dev)).cpu().numpy()
+            assert rel(y, A @ x) <= 1e-6, (nx, ny, kernel)
+            Hg.close()
+
+
+def test_zero_matrix_keeps_beta_y(torch_dev, hm):
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case("dip30_48x24")
+    for kernel in KERNELS:
+        Hb = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=1, kernel=kernel, **_opts(w))
+        y0 = torch.arange(f.n, dtype=torch.float64, device=dev)
+        y = y0.clone()
+        Hb.matvec(torch.ones(f.n, dtype=torch.float64, device=dev), y=y, alpha=1.0, beta=2.0)
+        assert torch.equal(y, 2.0 * y0)
+        Hb.close()
