@@ -159,6 +159,14 @@ __global__ __launch_bounds__(NW * 64) void k_units(BatchedArgs a, int first, con
                          red);
 }
 
+// Persistent schedule.  Thread 0 is the only thread that touches the queue:
+// at the top of each iteration it first publishes the completion of the
+// phase-1 unit the workgroup has just finished (if any), then takes the next
+// ticket; both atomics sit in one thread-0 region so that no lane can start
+// a new iteration before the ticket is refreshed.  Tickets are handed out in
+// order, so every phase-1 unit is owned by a running workgroup before any
+// phase-2 unit is taken; phase-2 units wait (all threads polling, no
+// divergent wait) until the phase-1 completion count reaches n1.
 template <typename T, int NW>
 __global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const double* __restrict__ x,
                                                         double* __restrict__ y, double alpha, double beta) {
@@ -167,26 +175,27 @@ __global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const dou
   __shared__ unsigned ticket;
   const unsigned n1 = (unsigned)a.n1, total = (unsigned)(a.n1 + a.n2);
   QueueCounters* ctr = a.ctr;
+  unsigned done_p1 = 0;  // 1 after a phase-1 unit, until it is published
   for (;;) {
-    if (threadIdx.x == 0) ticket = __hip_atomic_fetch_add(&ctr->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0) {
+      if (done_p1) __hip_atomic_fetch_add(&ctr->p1done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      ticket = __hip_atomic_fetch_add(&ctr->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
     __syncthreads();
-    const unsigned t = ticket;
+    const unsigned t = __builtin_amdgcn_readfirstlane(ticket);
     __syncthreads();
     if (t >= total) break;
     if (t >= n1) {
-      if (threadIdx.x == 0) {
-        while (__hip_atomic_load(&ctr->p1done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < n1)
-          __builtin_amdgcn_s_sleep(2);
-      }
-      __syncthreads();
+      while (__hip_atomic_load(&ctr->p1done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < n1)
+        __builtin_amdgcn_s_sleep(2);
     }
     const Unit u = a.units[t];
     run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.tinfo, a.tp, alpha, beta, zs,
                           red);
-    if (t < n1) {
-      __threadfence();
-      __syncthreads();
-      if (threadIdx.x == 0) __hip_atomic_fetch_add(&ctr->p1done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    done_p1 = t < n1 ? 1u : 0u;
+    if (done_p1) {
+      __threadfence();  // this thread's partial results visible device-wide
+      __syncthreads();  // ... for every thread, before thread 0 publishes
     }
   }
   if (threadIdx.x == 0) {
