@@ -142,8 +142,7 @@ struct hmat_s {
     batched.n1 = L.n1;
     batched.n2 = L.n2;
     batched.src = upload(L.src, s, true);
-    batched.tinfo = upload(L.tinfo, s, true);
-    batched.tp = alloc_zero<double>((size_t)L.tp_size, s, true);
+    batched.t = alloc_zero<double>((size_t)L.t_size, s, true);
     batched.pool = upload(L.pool, s, true);
     batched.perm = d_perm;
     batched.ctr = alloc_zero<hm::QueueCounters>(1, s, true);

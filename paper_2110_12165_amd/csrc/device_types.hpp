@@ -31,22 +31,18 @@ struct UnitEntry {
 // group stores, for every output lane, W consecutive inputs (16 bytes):
 //   panel[(q * nout + o) * W + c] = coefficient of input q*W + c for output o.
 // kind 1 (phase 1, t = V^T x): outputs are intermediate values of one column
-//   cluster, inputs are its rows in1 + [0, nin) (gathered from x through the
+//   cluster, inputs are its rows in0 + [0, nin) (gathered from x through the
 //   permutation; rows beyond nin are zero padding); result o goes to
-//   tp[out0 + o * ostride].
+//   t[out0 + o].
 // kind 2 (phase 2, y = D x + U t): outputs are rows out0 + [0, nout) in
 //   cluster order, inputs are described by src[in0 + i] (>= 0: element of x
-//   in user order; < 0: entry -src-1 of the tinfo table).
-// S: waves sharing the outputs side by side (outputs o = 64*(w % S) + lane),
-//   the remaining waves split the input groups.
+//   in user order; < 0: entry -src-1 of t, entry 0 being a zero pad).
+// Waves w < S*RG work: output group w % S (outputs 64*(w % S) + lane), input
+//   groups q = w / S (mod RG); partial sums of the RG input groups are added
+//   in LDS in a fixed order.
 struct Unit {
-  int32_t nout, nq, S, in0, nin, out0, ostride, kind;
+  int32_t nout, nq, S, RG, in0, nin, out0, kind;
   int64_t off;
-};
-
-// Intermediate value assembled from `count` partial sums tp[base + c].
-struct TInfo {
-  int32_t base, count;
 };
 
 // Counters of the persistent schedule; reset by the last workgroup to exit.

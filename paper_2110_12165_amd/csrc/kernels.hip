@@ -64,21 +64,22 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <typename T, int NW, bool COHERENT>
 __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ pool, const double* __restrict__ x,
                                          double* __restrict__ y, const int32_t* __restrict__ perm,
-                                         const int32_t* __restrict__ src, const TInfo* __restrict__ tinfo,
-                                         double* tp, double alpha, double beta, double* zs, double* red) {
+                                         const int32_t* __restrict__ src, double* t, double alpha, double beta,
+                                         double* zs, double* red) {
   using V = typename Pack<T>::vec;
   constexpr int W = Pack<T>::W;
+  constexpr int U = 8;  // loads in flight per lane
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  const int S = u.S;
-  const int RG = NW / S;
+  const int S = u.S, RG = u.RG;
+  const bool working = wave < S * RG;
   const int sg = wave % S, rg = wave / S;
   const int o = sg * 64 + lane;
-  const bool active = o < u.nout;
+  const bool active = working && o < u.nout;
   const int nin_pad = u.nq * W;
   const size_t stride = (size_t)u.nout;
   const V* base = reinterpret_cast<const V*>(pool + u.off) + o;
-  double a0 = 0.0, a1 = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
 
   for (int c0 = 0; c0 < nin_pad; c0 += kStage) {
     const int cl = min(kStage, nin_pad - c0);
@@ -89,12 +90,8 @@ __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ po
         if (gi < u.nin) v = x[perm[u.in0 + gi]];
       } else {
         const int s = src[u.in0 + gi];
-        if (s >= 0) {
-          v = x[s];
-        } else {
-          const TInfo ti = tinfo[-s - 1];
-          for (int c = 0; c < ti.count; ++c) v += COHERENT ? load_agent(tp + ti.base + c) : tp[ti.base + c];
-        }
+        if (s >= 0) v = x[s];
+        else v = COHERENT ? load_agent(t - s - 1) : t[-s - 1];
       }
       zs[i] = v;
     }
@@ -103,47 +100,41 @@ __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ po
       const int q0 = c0 / W;
       const int q1 = q0 + cl / W;
       int q = q0 + rg;
-      for (; q + 3 * RG < q1; q += 4 * RG) {
-        const V v0 = load_stream<T>(base + (size_t)q * stride);
-        const V v1 = load_stream<T>(base + (size_t)(q + RG) * stride);
-        const V v2 = load_stream<T>(base + (size_t)(q + 2 * RG) * stride);
-        const V v3 = load_stream<T>(base + (size_t)(q + 3 * RG) * stride);
-        const double* z0 = zs + (q - q0) * W;
-        const double* z1 = z0 + RG * W;
-        const double* z2 = z1 + RG * W;
-        const double* z3 = z2 + RG * W;
+      for (; q + (U - 1) * RG < q1; q += U * RG) {
+        V v[U];
 #pragma unroll
-        for (int c = 0; c < W; ++c) {
-          a0 = fma((double)v0[c], z0[c], a0);
-          a1 = fma((double)v1[c], z1[c], a1);
-          a0 = fma((double)v2[c], z2[c], a0);
-          a1 = fma((double)v3[c], z3[c], a1);
+        for (int k = 0; k < U; ++k) v[k] = load_stream<T>(base + (size_t)(q + k * RG) * stride);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const double* z = zs + (q + k * RG - q0) * W;
+#pragma unroll
+          for (int c = 0; c < W; ++c) acc[k & 3] = fma((double)v[k][c], z[c], acc[k & 3]);
         }
       }
       for (; q < q1; q += RG) {
         const V v0 = load_stream<T>(base + (size_t)q * stride);
-        const double* z0 = zs + (q - q0) * W;
+        const double* z = zs + (q - q0) * W;
 #pragma unroll
-        for (int c = 0; c < W; ++c) a0 = fma((double)v0[c], z0[c], a0);
+        for (int c = 0; c < W; ++c) acc[0] = fma((double)v0[c], z[c], acc[0]);
       }
     }
     __syncthreads();
   }
-  double acc = a0 + a1;
+  double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   if (RG > 1) {
-    red[wave * 64 + lane] = acc;
+    if (working) red[wave * 64 + lane] = sum;
     __syncthreads();
     if (rg == 0) {
-      acc = 0.0;
-      for (int r = 0; r < RG; ++r) acc += red[(r * S + sg) * 64 + lane];
+      sum = 0.0;
+      for (int r = 0; r < RG; ++r) sum += red[(r * S + sg) * 64 + lane];
     }
   }
   if (rg == 0 && active) {
     if (u.kind == 1) {
-      tp[u.out0 + (size_t)o * u.ostride] = acc;
+      t[u.out0 + o] = sum;
     } else {
       const int row = perm[u.out0 + o];
-      y[row] = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * y[row]);
+      y[row] = beta == 0.0 ? alpha * sum : fma(alpha, sum, beta * y[row]);
     }
   }
   __syncthreads();
@@ -155,8 +146,7 @@ __global__ __launch_bounds__(NW * 64) void k_units(BatchedArgs a, int first, con
   __shared__ double zs[kStage];
   __shared__ double red[NW * 64];
   const Unit u = a.units[first + blockIdx.x];
-  run_unit<T, NW, false>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.tinfo, a.tp, alpha, beta, zs,
-                         red);
+  run_unit<T, NW, false>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, alpha, beta, zs, red);
 }
 
 // Persistent schedule.  Thread 0 is the only thread that touches the queue:
@@ -190,8 +180,7 @@ __global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const dou
         __builtin_amdgcn_s_sleep(2);
     }
     const Unit u = a.units[t];
-    run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.tinfo, a.tp, alpha, beta, zs,
-                          red);
+    run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, alpha, beta, zs, red);
     done_p1 = t < n1 ? 1u : 0u;
     if (done_p1) {
       __threadfence();  // this thread's partial results visible device-wide

@@ -28,8 +28,7 @@ struct BatchedArgs {
   const Unit* units;
   int32_t n1, n2;
   const int32_t* src;
-  const TInfo* tinfo;
-  double* tp;  // scratch: partial intermediate values
+  double* t;  // scratch: intermediate values t = V^T x, t[0] = 0
   const void* pool;
   const int32_t* perm;
   QueueCounters* ctr;

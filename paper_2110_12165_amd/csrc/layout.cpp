@@ -139,11 +139,16 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
   const int64_t nb = H.nblocks();
 
   // ---- phase 1: group low-rank blocks by their column cluster -------------
+  // Every unit covers all rows of its cluster, so each intermediate value is
+  // produced by exactly one unit (no partial sums).  Waves of a unit split
+  // the rows into RG groups (at least kMinQuads input groups each) and the
+  // outputs into S groups of 64.
+  constexpr int64_t kMinQuads = 16;
   struct Group {
     int64_t c0, n;
     std::vector<int32_t> blocks;
-    int64_t R = 0, C = 1, rc = 0, base = 0;
-    int S = 1;
+    int64_t R = 0, base = 0;
+    int S = 1, RG = 1;
   };
   std::vector<Group> groups;
   std::map<std::pair<int64_t, int64_t>, size_t> gid;
@@ -154,39 +159,30 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     auto it = gid.find(key);
     if (it == gid.end()) {
       it = gid.emplace(key, groups.size()).first;
-      groups.push_back(Group{d[3], d[4], {}, 0, 1, 0, 0, 1});
+      groups.push_back(Group{d[3], d[4], {}, 0, 0, 1, 1});
     }
     groups[it->second].blocks.push_back((int32_t)b);
     groups[it->second].R += d[5];
   }
-  // intermediate slot numbering: tinfo[0] is the zero entry
-  std::vector<int64_t> slot_of_block(nb, -1);  // tinfo index of (block, column 0)
-  L.tinfo.push_back({0, 0});
-  int64_t tp = 0;
+  std::vector<int64_t> slot_of_block(nb, -1);  // t index of (block, column 0)
+  int64_t t = 1;                                // t[0] is the zero pad
   for (auto& g : groups) {
-    const int64_t need_waves = (g.R + 63) / 64;
-    g.S = 1;
-    while (g.S < need_waves && g.S < wg_waves) g.S *= 2;
-    const int64_t NS = 64LL * g.S;
-    const int64_t full = NS * g.n * (int64_t)sizeof(T);
-    g.C = std::max<int64_t>(1, (full + unit_bytes - 1) / unit_bytes);
-    g.rc = (g.n + g.C - 1) / g.C;
-    g.rc = (g.rc + W - 1) / W * W;
-    g.C = (g.n + g.rc - 1) / g.rc;
-    g.base = tp;
-    tp += g.R * g.C;
-    int64_t s = 0;
+    const int64_t nq = (g.n + W - 1) / W;
+    g.RG = (int)std::max<int64_t>(1, std::min<int64_t>(wg_waves, nq / kMinQuads));
+    const int64_t need = (g.R + 63) / 64;
+    g.S = (int)std::max<int64_t>(1, std::min<int64_t>(need, wg_waves / g.RG));
+    while (g.S > 1 && 64LL * g.S * g.n * (int64_t)sizeof(T) > unit_bytes) --g.S;
+    g.base = t;
     for (int32_t b : g.blocks) {
-      slot_of_block[b] = (int64_t)L.tinfo.size();
-      for (int64_t k = 0; k < H.desc[6 * b + 5]; ++k, ++s)
-        L.tinfo.push_back({to_i32(g.base + s * g.C, "partial index"), (int32_t)g.C});
+      slot_of_block[b] = t;
+      t += H.desc[6 * b + 5];
     }
   }
-  L.tp_size = std::max<int64_t>(tp, 1);
-  to_i32((int64_t)L.tinfo.size() + 2, "intermediate slots");
+  L.t_size = t;
+  to_i32(t + 1, "intermediate values");
 
   std::vector<Unit> p1, p2;
-  struct Pending { Unit u; int kind; size_t g; int64_t s0, j0; int64_t q_off; };
+  struct Pending { Unit u; int kind; size_t g; int64_t s0; };
   int64_t off = 0;
   std::vector<Pending> pend;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -194,22 +190,18 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     const int64_t NS = 64LL * g.S;
     for (int64_t s0 = 0; s0 < g.R; s0 += NS) {
       const int64_t ns = std::min(NS, g.R - s0);
-      for (int64_t c = 0; c < g.C; ++c) {
-        const int64_t j0 = c * g.rc;
-        const int64_t nin = std::min(g.rc, g.n - j0);
-        Unit u;
-        u.kind = 1;
-        u.nout = (int32_t)ns;
-        u.nq = to_i32((nin + W - 1) / W, "unit inputs");
-        u.S = g.S;
-        u.in0 = to_i32(g.c0 + j0, "row");
-        u.nin = (int32_t)nin;
-        u.out0 = to_i32(g.base + s0 * g.C + c, "partial index");
-        u.ostride = (int32_t)g.C;
-        u.off = off = align_elems<T>(off);
-        off += (int64_t)u.nq * W * ns;
-        pend.push_back({u, 1, gi, s0, j0, 0});
-      }
+      Unit u;
+      u.kind = 1;
+      u.nout = (int32_t)ns;
+      u.nq = to_i32((g.n + W - 1) / W, "unit inputs");
+      u.S = (int32_t)((ns + 63) / 64);
+      u.RG = g.RG;
+      u.in0 = to_i32(g.c0, "row");
+      u.nin = (int32_t)g.n;
+      u.out0 = to_i32(g.base + s0, "intermediate index");
+      u.off = off = align_elems<T>(off);
+      off += (int64_t)u.nq * W * ns;
+      pend.push_back({u, 1, gi, s0});
     }
   }
   // ---- phase 2: one unit per refined row interval --------------------------
@@ -220,9 +212,9 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     u.kind = 2;
     u.nout = (int32_t)m;
     u.S = 1;
+    u.RG = wg_waves;
     u.in0 = to_i32((int64_t)L.src.size(), "input list");
     u.out0 = (int32_t)a;
-    u.ostride = 1;
     int64_t K = 0;
     // dense columns first, then low-rank columns
     for (int pass = 0; pass < 2; ++pass)
@@ -244,7 +236,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     u.nin = (int32_t)K;
     u.off = off = align_elems<T>(off);
     off += K * m;
-    pend.push_back({u, 2, k, 0, 0, 0});
+    pend.push_back({u, 2, k, 0});
   }
   to_i32((int64_t)L.src.size(), "input list");
   L.pool.assign(align_elems<T>(off) + 256 / sizeof(T), T(0));
@@ -273,7 +265,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
           const double* V = &H.values[H.off[b] + m * r];
           for (int c = 0; c < W; ++c) {
             const int64_t j = q * W + c;
-            dst[(q * u.nout + o) * W + c] = j < u.nin ? (T)V[kk * n + p.j0 + j] : T(0);
+            dst[(q * u.nout + o) * W + c] = j < u.nin ? (T)V[kk * n + j] : T(0);
           }
         }
     } else {

@@ -33,8 +33,7 @@ struct BatchedLayout {
   std::vector<Unit> units;             // n1 phase-1 units, then n2 phase-2 units
   int32_t n1 = 0, n2 = 0;
   std::vector<int32_t> src;
-  std::vector<TInfo> tinfo;
-  int64_t tp_size = 0;
+  int64_t t_size = 0;                  // intermediate values, entry 0 = zero pad
   int32_t wg_waves = 8;
   int64_t unit_bytes = 0;
 };

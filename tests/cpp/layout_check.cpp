@@ -1,0 +1,188 @@
+// CPU replay of the batched product's indexing (test infrastructure).
+//
+// Builds the blocks of a planar grid with the library's host construction,
+// packs them with make_batched for several workgroup shapes, then walks
+// every unit exactly as the HIP kernel does (same stage rounds, waves,
+// lanes, input groups and reduction slots), asserting that every access
+// stays inside its buffer, and compares the result with a direct product
+// over the blocks.  Also checks that every panel entry is read exactly once.
+//
+// usage: layout_check nx ny h dip slip(0 strike,1 dip) leaf lattice eps
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <memory>
+#include <vector>
+
+#include "hmat_internal.hpp"
+#include "layout.hpp"
+
+using namespace hm;
+
+static void die(const char* m, long a = 0, long b = 0) {
+  std::fprintf(stderr, "FAIL: %s (%ld, %ld)\n", m, a, b);
+  std::exit(1);
+}
+
+template <typename T>
+static double replay(const HostMatrix& H, int NW, int64_t unit_bytes, const std::vector<double>& x,
+                     const std::vector<double>& yref) {
+  constexpr int W = 16 / (int)sizeof(T);
+  constexpr int kStage = 2048;
+  BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes);
+  const int64_t n = H.n;
+  std::vector<double> t(L.t_size, 0.0), y(n, 0.0);
+  std::vector<unsigned char> touched(L.pool.size(), 0);
+  std::vector<int> y_written(n, 0);
+  std::vector<int> t_written(L.t_size, 0);
+  for (int pass = 1; pass <= 2; ++pass) {
+    for (int32_t ui = 0; ui < L.n1 + L.n2; ++ui) {
+      const Unit& u = L.units[ui];
+      if (u.kind != pass) continue;
+      if (ui < L.n1 && u.kind != 1) die("phase-2 unit among phase-1 units", ui);
+      if (u.S < 1 || u.RG < 1 || u.S * u.RG > NW) die("bad S/RG", u.S, u.RG);
+      if (u.nout < 1 || u.nout > 64 * u.S) die("bad nout", u.nout, u.S);
+      const int nin_pad = u.nq * W;
+      std::vector<double> zs(kStage), red((size_t)NW * 64, 0.0);
+      std::vector<double> acc((size_t)NW * 64, 0.0);
+      for (int c0 = 0; c0 < nin_pad; c0 += kStage) {
+        const int cl = std::min(kStage, nin_pad - c0);
+        if (cl % W) die("stage not a multiple of W", cl);
+        for (int i = 0; i < cl; ++i) {
+          const int gi = c0 + i;
+          double v = 0.0;
+          if (u.kind == 1) {
+            if (gi < u.nin) {
+              if (u.in0 + gi >= n) die("perm index", u.in0 + gi);
+              v = x[H.perm[u.in0 + gi]];
+            }
+          } else {
+            if ((int64_t)u.in0 + gi >= (int64_t)L.src.size()) die("src index", u.in0 + gi);
+            const int s = L.src[u.in0 + gi];
+            if (s >= 0) {
+              if (s >= n) die("x index", s);
+              v = x[s];
+            } else {
+              if (-s - 1 >= L.t_size) die("t index", -s - 1);
+              if (-s - 1 > 0 && !t_written[-s - 1]) die("t read before written", -s - 1);
+              v = t[-s - 1];
+            }
+          }
+          zs[i] = v;
+        }
+        for (int wave = 0; wave < NW; ++wave) {
+          const bool working = wave < u.S * u.RG;
+          const int sg = wave % u.S, rg = wave / u.S;
+          for (int lane = 0; lane < 64; ++lane) {
+            const int o = sg * 64 + lane;
+            if (!(working && o < u.nout)) continue;
+            const int q0 = c0 / W, q1 = q0 + cl / W;
+            for (int q = q0 + rg; q < q1; q += u.RG) {
+              for (int c = 0; c < W; ++c) {
+                const int64_t e = u.off + ((int64_t)q * u.nout + o) * W + c;
+                if (e < 0 || e >= (int64_t)L.pool.size()) die("pool index", (long)e);
+                if (touched[e]++) die("panel entry read twice", (long)e);
+                const int zi = (q - q0) * W + c;
+                if (zi < 0 || zi >= cl) die("stage index", zi);
+                acc[wave * 64 + lane] += (double)L.pool[e] * zs[zi];
+              }
+            }
+          }
+        }
+      }
+      for (int wave = 0; wave < NW; ++wave) {
+        const int sg = wave % u.S, rg = wave / u.S;
+        if (rg != 0) continue;
+        for (int lane = 0; lane < 64; ++lane) {
+          const int o = sg * 64 + lane;
+          if (o >= u.nout) continue;
+          double sum = 0.0;
+          for (int r = 0; r < u.RG; ++r) {
+            const int idx = (r * u.S + sg) * 64 + lane;
+            if (idx >= NW * 64) die("reduction index", idx);
+            sum += acc[idx];
+          }
+          if (u.kind == 1) {
+            const int64_t ti = (int64_t)u.out0 + o;
+            if (ti < 1 || ti >= L.t_size) die("t output index", (long)ti);
+            if (t_written[ti]++) die("t written twice", (long)ti);
+            t[ti] = sum;
+          } else {
+            const int64_t row = (int64_t)u.out0 + o;
+            if (row < 0 || row >= n) die("row index", (long)row);
+            if (y_written[row]++) die("row written twice", (long)row);
+            y[H.perm[row]] = sum;
+          }
+        }
+      }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i)
+    if (y_written[i] != 1) die("row not written once", (long)i, y_written[i]);
+  // every non-padding panel entry must have been read (padding entries are 0)
+  for (size_t e = 0; e < L.pool.size(); ++e)
+    if (!touched[e] && L.pool[e] != T(0)) die("nonzero panel entry never read", (long)e);
+  double num = 0.0, den = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    num += (y[i] - yref[i]) * (y[i] - yref[i]);
+    den += yref[i] * yref[i];
+  }
+  return std::sqrt(num / den);
+}
+
+int main(int argc, char** argv) {
+  if (argc != 9) die("usage");
+  const int nx = std::atoi(argv[1]), ny = std::atoi(argv[2]);
+  const double h = std::atof(argv[3]), dip = std::atof(argv[4]);
+  const int slip = std::atoi(argv[5]), leaf = std::atoi(argv[6]), lattice = std::atoi(argv[7]);
+  const double eps = std::atof(argv[8]);
+  const int64_t n = (int64_t)nx * ny;
+  // planar grid of squares, as the synthetic workloads build it
+  const double c = dip == 90.0 ? 0.0 : std::cos(dip * M_PI / 180.0);
+  const double s = dip == 90.0 ? 1.0 : std::sin(dip * M_PI / 180.0);
+  std::vector<double> verts(n * 12), sd(n * 3);
+  for (int64_t k = 0; k < n; ++k) {
+    const int64_t iy = k / nx, ix = k % nx;
+    const double xs[4] = {ix * h, (ix + 1) * h, (ix + 1) * h, ix * h};
+    const double ds[4] = {iy * h, iy * h, (iy + 1) * h, (iy + 1) * h};
+    for (int v = 0; v < 4; ++v) {
+      verts[k * 12 + 3 * v] = xs[v];
+      verts[k * 12 + 3 * v + 1] = ds[v] * c;
+      verts[k * 12 + 3 * v + 2] = -ds[v] * s;
+    }
+    if (slip == 0) { sd[3 * k] = 1; sd[3 * k + 1] = 0; sd[3 * k + 2] = 0; }
+    else { sd[3 * k] = 0; sd[3 * k + 1] = -c; sd[3 * k + 2] = s; }
+  }
+  hmat_mesh mesh{n, 4, verts.data(), sd.data()};
+  hmat_green green{HMAT_GF_FS_RECT_COPLANAR, 0, 32e9, 0.25};
+  Geometry geo;
+  std::unique_ptr<EntryFn> E(make_entry_fn(mesh, green, geo));
+  ClusterTree tree = build_tree(geo, leaf);
+  HostMatrix H = assemble(*E, tree, partition(tree, lattice, 2.0), eps, 0, 0);
+  std::vector<double> x(n), yref(n, 0.0), yc(n, 0.0);
+  for (int64_t i = 0; i < n; ++i) x[i] = std::pow(10.0, -12.0 + 3.0 * std::fmod(0.6180339887 * (i + 1), 1.0));
+  for (int64_t b = 0; b < H.nblocks(); ++b) {  // direct product over the blocks
+    const int64_t* d = &H.desc[6 * b];
+    const double* v = &H.values[H.off[b]];
+    if (d[0] == 0) {
+      for (int64_t j = 0; j < d[4]; ++j)
+        for (int64_t i = 0; i < d[2]; ++i) yc[d[1] + i] += v[j * d[2] + i] * x[H.perm[d[3] + j]];
+    } else {
+      for (int64_t k = 0; k < d[5]; ++k) {
+        double tk = 0.0;
+        for (int64_t j = 0; j < d[4]; ++j) tk += v[d[2] * d[5] + k * d[4] + j] * x[H.perm[d[3] + j]];
+        for (int64_t i = 0; i < d[2]; ++i) yc[d[1] + i] += v[k * d[2] + i] * tk;
+      }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) yref[H.perm[i]] = yc[i];
+  for (int NW : {4, 8, 16})
+    for (int64_t ub : {64 << 10, 256 << 10, 4 << 20}) {
+      const double r64 = replay<double>(H, NW, ub, x, yref);
+      const double r32 = replay<float>(H, NW, ub, x, yref);
+      std::printf("NW=%d unit=%ld rel64=%.3e rel32=%.3e\n", NW, (long)ub, r64, r32);
+      if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed product differs");
+    }
+  std::printf("OK\n");
+  return 0;
+}
