@@ -30,6 +30,20 @@ WORKLOAD = "dip30_480x256"
 HBM_PEAK_GBS = 8000.0
 
 
+# Dominant kernel of each schedule (launch index -> kernel symbol of the FP32 build).
+DOMINANT_SYMBOL = {
+    ("split", 1): "k_phase<float, 4, 2> (phase 2: y = D x + U t)",
+    ("split", 0): "k_phase<float, 4, 1> (phase 1: t = V^T x)",
+    ("persistent", 0): "k_persistent<float, 4>",
+    ("plain", 1): "k_plain_p2<float>",
+    ("plain", 0): "k_plain_p1<float>",
+}
+# HBM traffic per dominant-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
+# (scaled by a plain copy of known size), for the kernel as it currently is; None until
+# measured for this code.
+TRAFFIC = {}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -113,6 +127,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="batched_f32,plain_f64,batched_f64")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: the product is not sharded across GPUs in this build "
@@ -134,6 +150,12 @@ def main():
     f = config_fault(WORKLOAD)
     x_np = loguniform_rates(f.n, w["seed"])
     x = torch.tensor(x_np, device=dev)
+    if args.calib_copy_mib:
+        src_buf = torch.ones(args.calib_copy_mib * (1 << 18), dtype=torch.float32, device=dev)
+        dst_buf = torch.empty_like(src_buf)
+        dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
     results = {}
     outputs = {}
     for variant in args.variants.split(","):
@@ -146,14 +168,22 @@ def main():
         y = torch.empty_like(x)
         log(f"[bench] {variant}: built in {build_s:.1f} s; kernel {info['kernel']}, "
             f"{info['factor_bytes'] / 1e9:.3f} GB of factors")
-        ms, launch_ms, wall_ms = time_products(torch, H, x, y, args.steps, args.warmup)
+        ms, product_ms, wall_ms = time_products(torch, H, x, y, args.steps, args.warmup)
         outputs[variant] = H.matvec(x).cpu().numpy()
-        achieved = info["alg_bytes"] / (launch_ms * 1e-3) / 1e9
-        results[variant] = dict(ms=ms, launch_ms=launch_ms, wall_ms=wall_ms, matvec_per_s=1e3 / ms,
-                                alg_bytes=info["alg_bytes"], achieved_gbs=achieved,
-                                hbm_frac=achieved / HBM_PEAK_GBS, build_s=build_s, info=info)
-        log(f"[bench] {variant}: {1e3 / ms:.1f} matvec/s, launch {launch_ms * 1e3:.1f} us, "
-            f"{achieved:.0f} GB/s ({100 * achieved / HBM_PEAK_GBS:.1f}% of HBM)")
+        # per-launch durations from HIP events recorded by the library on this stream
+        pr = H.profile(x, y, reps=args.steps)
+        dom = int(np.argmax(pr["ms"]))
+        launches = [dict(alg_bytes=b, ms=m, achieved_gbs=b / (m * 1e-3) / 1e9)
+                    for b, m in zip(pr["alg_bytes"], pr["ms"])]
+        achieved = launches[dom]["achieved_gbs"]
+        whole = info["alg_bytes"] / (ms * 1e-3) / 1e9
+        results[variant] = dict(ms=ms, product_ms=product_ms, wall_ms=wall_ms, matvec_per_s=1e3 / ms,
+                                alg_bytes=info["alg_bytes"], achieved_gbs=achieved, dominant_launch=dom,
+                                launches=launches, hbm_frac=achieved / HBM_PEAK_GBS,
+                                product_gbs=whole, product_hbm_frac=whole / HBM_PEAK_GBS, build_s=build_s, info=info)
+        log(f"[bench] {variant}: {1e3 / ms:.1f} matvec/s ({ms * 1e3:.1f} us/product, {whole:.0f} GB/s = "
+            f"{100 * whole / HBM_PEAK_GBS:.1f}% of HBM over the product); launches "
+            + ", ".join(f"{l['ms'] * 1e3:.1f} us {l['achieved_gbs']:.0f} GB/s" for l in launches))
         H.close()
         torch.cuda.empty_cache()
 
@@ -187,13 +217,20 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["hbm_frac"],
-            "traffic": None,
+            "traffic": TRAFFIC.get(info["kernel"]),
+            "kernel": DOMINANT_SYMBOL.get((info["kernel"], head["dominant_launch"]), "?"),
+            "launch_alg_bytes": head["launches"][head["dominant_launch"]]["alg_bytes"],
+            "launch_ms": head["launches"][head["dominant_launch"]]["ms"],
+            "launches": head["launches"],
+            "product_gbs": head["product_gbs"],
+            "product_frac": head["product_hbm_frac"],
         },
         "hmat": {k: info[k] for k in ("n_dense", "n_lr", "dense_entries", "lr_entries", "max_rank", "sum_rank",
                                       "factor_bytes", "alg_bytes", "n_units_p1", "n_units_p2")},
     }
     for v, r in results.items():
-        line[v] = {k: r[k] for k in ("matvec_per_s", "ms", "launch_ms", "achieved_gbs", "hbm_frac", "build_s")}
+        line[v] = {k: r[k] for k in ("matvec_per_s", "ms", "product_gbs", "product_hbm_frac", "achieved_gbs",
+                                     "hbm_frac", "build_s")}
         line[v]["kernel"] = r["info"]["kernel"]
     if "plain_f64" in results:
         line["speedup_batched_f32_vs_plain_f64"] = head["matvec_per_s"] / results["plain_f64"]["matvec_per_s"]

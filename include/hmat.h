@@ -223,6 +223,26 @@ hmat_status hmat_info(hmat_t h, hmat_stats* out);
  */
 hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream);
 
+/* Launch timings of the product (hmat_profile). */
+typedef struct {
+  int32_t n_launches;      /* kernel launches per product: 2 (plain, split) or 1 (persistent) */
+  int32_t reps;
+  double ms[2];            /* mean duration of each launch [ms] (HIP events on the stream) */
+  double ms_product;       /* mean duration of a whole product [ms] */
+  int64_t alg_bytes[2];    /* algorithmic bytes of each launch: launch 1 (phase 1) reads the
+                              V factors, x and the permutation and writes t; launch 2 (phase 2)
+                              reads the dense blocks, the U factors, t, x, the permutation and
+                              reads/writes y.  A single persistent launch reports alg_bytes. */
+} hmat_profile_t;
+
+/*
+ * hmat_profile — run reps products y = H x (after one warm-up) with HIP
+ * events around each kernel launch on `stream` and report mean durations.
+ * x, y: DEVICE FP64 vectors of length n (not overlapping).  Synchronises the
+ * stream; creates and destroys its own events.
+ */
+hmat_status hmat_profile(hmat_t h, const double* x, double* y, int32_t reps, void* stream, hmat_profile_t* out);
+
 /* Rate-and-state parameters for rs_rhs (section 2.2; section 4.1 loading). */
 typedef struct {
   int64_t n;               /* elements; must equal the order of A (and B) */

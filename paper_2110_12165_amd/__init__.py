@@ -45,6 +45,7 @@ class HMatrix:
     def __init__(self, handle):
         self._h = handle
         self._lib = _lib.load()
+        self._n = None
 
     # -- construction -------------------------------------------------------
     @staticmethod
@@ -145,7 +146,9 @@ class HMatrix:
 
     @property
     def n(self):
-        return self.info()["n"]
+        if self._n is None:
+            self._n = self.info()["n"]
+        return self._n
 
     def export(self):
         """Copies of the FP64 host blocks: dict(n, perm, desc (nb, 6), off, values)."""
@@ -157,6 +160,14 @@ class HMatrix:
                     desc=np.ctypeslib.as_array(hb.desc, shape=(nb * 6,)).copy().reshape(nb, 6),
                     off=np.ctypeslib.as_array(hb.off, shape=(nb,)).copy(),
                     values=np.ctypeslib.as_array(hb.values, shape=(nv,)).copy() if nv else np.zeros(0))
+
+    def profile(self, x, y, reps=50, stream=None):
+        """hmat_profile: per-launch mean durations (ms) and algorithmic bytes."""
+        pr = _lib.HmatProfile()
+        check(self._lib.hmat_profile(self._h, _dptr(x), _dptr(y), reps, _stream_ptr(stream), C.byref(pr)))
+        nl = pr.n_launches
+        return dict(n_launches=nl, reps=pr.reps, ms=[pr.ms[i] for i in range(nl)], ms_product=pr.ms_product,
+                    alg_bytes=[pr.alg_bytes[i] for i in range(nl)])
 
     def autotune(self, reps=20, stream=None):
         check(self._lib.hmat_autotune(self._h, reps, _stream_ptr(stream)))

@@ -44,6 +44,11 @@ class HmatHostBlocks(C.Structure):
                 ("off", C.POINTER(C.c_int64)), ("values", C.POINTER(C.c_double))]
 
 
+class HmatProfile(C.Structure):
+    _fields_ = [("n_launches", C.c_int32), ("reps", C.c_int32), ("ms", C.c_double * 2), ("ms_product", C.c_double),
+                ("alg_bytes", C.c_int64 * 2)]
+
+
 class RsParams(C.Structure):
     _fields_ = [("n", C.c_int64), ("V0", C.c_double), ("f0", C.c_double), ("eta_rad", C.c_double),
                 ("V_pl", C.c_double), ("a", C.c_void_p), ("b", C.c_void_p), ("dc", C.c_void_p)]
@@ -64,6 +69,7 @@ SIGNATURES = {
                                 C.c_void_p]),
     "hmat_info": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
     "hmat_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
+    "hmat_profile": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(HmatProfile)]),
     "rs_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
                          C.c_void_p]),
     "hmat_destroy": (None, [C.c_void_p]),

@@ -163,13 +163,13 @@ struct hmat_s {
   }
 
   hipError_t product(bool transpose, const double* x, double* y, double alpha, double beta, hipStream_t s,
-                     int32_t kern) const {
+                     int32_t kern, hipEvent_t* ev = nullptr) const {
     if (transpose || kern == HMAT_KERNEL_PLAIN)
-      return f32() ? hm::launch_plain<float>(plain, transpose, x, y, alpha, beta, s)
-                   : hm::launch_plain<double>(plain, transpose, x, y, alpha, beta, s);
+      return f32() ? hm::launch_plain<float>(plain, transpose, x, y, alpha, beta, s, ev)
+                   : hm::launch_plain<double>(plain, transpose, x, y, alpha, beta, s, ev);
     const bool pers = kern == HMAT_KERNEL_BATCHED_PERSISTENT;
-    return f32() ? hm::launch_batched<float>(batched, pers, grid, x, y, alpha, beta, s)
-                 : hm::launch_batched<double>(batched, pers, grid, x, y, alpha, beta, s);
+    return f32() ? hm::launch_batched<float>(batched, pers, grid, x, y, alpha, beta, s, ev)
+                 : hm::launch_batched<double>(batched, pers, grid, x, y, alpha, beta, s, ev);
   }
 };
 
@@ -191,7 +191,10 @@ void check_opts(const hmat_opts& o, bool build) {
   if (o.unit_kib < 0) hm::fail(HMAT_EINVAL, "unit_kib must be >= 0");
 }
 
-constexpr int32_t kDefaultWaves = 8;
+// Default schedule of the batched product (fastest measured on MI355X for
+// the planar benchmark fault; hmat_autotune can pick another).
+constexpr int32_t kAutoKernel = HMAT_KERNEL_BATCHED_SPLIT;
+constexpr int32_t kDefaultWaves = 4;
 constexpr int32_t kDefaultUnitKiB = 256;
 
 void fill_stats(hmat_s* h);
@@ -200,7 +203,7 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
   auto h = std::make_unique<hmat_s>();
   h->H = std::move(H);
   h->opts = o;
-  h->kernel = o.kernel == HMAT_KERNEL_AUTO ? HMAT_KERNEL_BATCHED_SPLIT : o.kernel;
+  h->kernel = o.kernel == HMAT_KERNEL_AUTO ? kAutoKernel : o.kernel;
   if (!on_device) {
     fill_stats(h.get());
     return h.release();
@@ -441,6 +444,55 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
     h->kernel = best_k;
     if (best_k != HMAT_KERNEL_PLAIN) h->setup_batched_any(best_w, (int64_t)best_u * 1024, s);
     refresh_stats(h);
+  });
+}
+
+hmat_status hmat_profile(hmat_t h, const double* x, double* y, int32_t reps, void* stream, hmat_profile_t* out) {
+  return guarded([&] {
+    check_vectors(h, x, y, 1, h ? h->H.n : 0);
+    if (!out) hm::fail(HMAT_EINVAL, "null output");
+    if (reps < 1) hm::fail(HMAT_EINVAL, "reps must be >= 1");
+    DeviceGuard g(h->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const bool pers = h->kernel == HMAT_KERNEL_BATCHED_PERSISTENT;
+    const int nl = pers ? 1 : 2;
+    std::vector<hipEvent_t> ev(3 * (size_t)reps, nullptr);
+    struct Destroy {
+      std::vector<hipEvent_t>& e;
+      ~Destroy() { for (auto v : e) if (v) (void)hipEventDestroy(v); }
+    } destroy{ev};
+    for (auto& e : ev) check_hip(hipEventCreate(&e), "hipEventCreate");
+    check_hip(h->product(false, x, y, 1.0, 0.0, s, h->kernel), "product launch");  // warm-up
+    for (int r = 0; r < reps; ++r) check_hip(h->product(false, x, y, 1.0, 0.0, s, h->kernel, &ev[3 * r]), "product launch");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    double sum[2] = {0.0, 0.0}, tot = 0.0;
+    for (int r = 0; r < reps; ++r) {
+      float a = 0.f, b = 0.f;
+      check_hip(hipEventElapsedTime(&a, ev[3 * r], ev[3 * r + 1]), "hipEventElapsedTime");
+      sum[0] += a;
+      if (nl == 2) {
+        check_hip(hipEventElapsedTime(&b, ev[3 * r + 1], ev[3 * r + 2]), "hipEventElapsedTime");
+        sum[1] += b;
+      }
+      tot += (double)a + (double)b;
+    }
+    const hmat_stats& st = h->st;
+    const int64_t n = st.n, sz = h->f32() ? 4 : 8;
+    // algorithmic bytes of each launch: its factors plus the vectors it must touch
+    int64_t lr_cols = 0, lr_rows = 0;  // sum r*n and sum r*m over low-rank blocks
+    for (int64_t b = 0; b < h->H.nblocks(); ++b) {
+      const int64_t* d = &h->H.desc[6 * b];
+      if (d[0] == 1) { lr_cols += d[5] * d[4]; lr_rows += d[5] * d[2]; }
+    }
+    const int64_t p1 = sz * lr_cols + 12 * n + 8 * st.sum_rank;
+    const int64_t p2 = sz * (st.dense_entries + lr_rows) + 8 * st.sum_rank + 28 * n;
+    out->n_launches = nl;
+    out->reps = reps;
+    out->ms[0] = sum[0] / reps;
+    out->ms[1] = nl == 2 ? sum[1] / reps : 0.0;
+    out->ms_product = tot / reps;
+    out->alg_bytes[0] = nl == 2 ? p1 : st.alg_bytes;
+    out->alg_bytes[1] = nl == 2 ? p2 : 0;
   });
 }
 

@@ -140,23 +140,29 @@ __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ po
   __syncthreads();
 }
 
-template <typename T, int NW>
-__global__ __launch_bounds__(NW * 64) void k_units(BatchedArgs a, int first, const double* __restrict__ x,
+// Split schedule: one launch per phase (distinct symbols), one workgroup per
+// unit, units in decreasing size.
+template <typename T, int NW, int PHASE>
+__global__ __launch_bounds__(NW * 64) void k_phase(BatchedArgs a, const double* __restrict__ x,
                                                    double* __restrict__ y, double alpha, double beta) {
   __shared__ double zs[kStage];
   __shared__ double red[NW * 64];
-  const Unit u = a.units[first + blockIdx.x];
+  const Unit u = a.units[(PHASE == 1 ? 0 : a.n1) + blockIdx.x];
   run_unit<T, NW, false>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, alpha, beta, zs, red);
 }
 
-// Persistent schedule.  Thread 0 is the only thread that touches the queue:
-// at the top of each iteration it first publishes the completion of the
-// phase-1 unit the workgroup has just finished (if any), then takes the next
-// ticket; both atomics sit in one thread-0 region so that no lane can start
-// a new iteration before the ticket is refreshed.  Tickets are handed out in
-// order, so every phase-1 unit is owned by a running workgroup before any
-// phase-2 unit is taken; phase-2 units wait (all threads polling, no
-// divergent wait) until the phase-1 completion count reaches n1.
+// Persistent schedule: one launch; workgroups take units in ticket order
+// (all phase-1 units come first).  Thread 0 alone touches the ticket counter,
+// in a region at the top of the loop followed by a barrier.  Cross-workgroup
+// visibility of the intermediate values costs an L2 write-back / invalidate
+// on this GPU, so it is paid at most once per workgroup and direction:
+//   - a workgroup counts the phase-1 units it finished and publishes the
+//     count (after every thread's release fence) only when it draws its
+//     first phase-2 ticket or runs out of work;
+//   - before its first phase-2 unit, wave 0 waits (acquire) until the
+//     published count reaches n1; later units skip the wait.
+// A workgroup publishes before it waits, and every phase-1 unit is held by a
+// running workgroup once any phase-2 ticket exists, so the wait ends.
 template <typename T, int NW>
 __global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const double* __restrict__ x,
                                                         double* __restrict__ y, double alpha, double beta) {
@@ -165,27 +171,37 @@ __global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const dou
   __shared__ unsigned ticket;
   const unsigned n1 = (unsigned)a.n1, total = (unsigned)(a.n1 + a.n2);
   QueueCounters* ctr = a.ctr;
-  unsigned done_p1 = 0;  // 1 after a phase-1 unit, until it is published
+  const int wave = threadIdx.x >> 6;
+  unsigned pending = 0;  // phase-1 units finished, not yet published (uniform)
+  bool ready = false;    // this workgroup has seen all phase-1 units done (uniform)
   for (;;) {
-    if (threadIdx.x == 0) {
-      if (done_p1) __hip_atomic_fetch_add(&ctr->p1done, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      ticket = __hip_atomic_fetch_add(&ctr->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (threadIdx.x == 0) ticket = __hip_atomic_fetch_add(&ctr->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     const unsigned t = __builtin_amdgcn_readfirstlane(ticket);
     __syncthreads();
+    if (t >= n1 && pending) {
+      __threadfence();
+      __syncthreads();
+      if (threadIdx.x == 0)
+        __hip_atomic_fetch_add(&ctr->p1done, pending, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      pending = 0;
+    }
     if (t >= total) break;
-    if (t >= n1) {
-      while (__hip_atomic_load(&ctr->p1done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < n1)
-        __builtin_amdgcn_s_sleep(2);
+    if (t >= n1 && !ready) {
+      if (wave == 0) {
+        for (;;) {
+          const unsigned d = __builtin_amdgcn_readfirstlane(
+              __hip_atomic_load(&ctr->p1done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+          if (d >= n1) break;
+          __builtin_amdgcn_s_sleep(2);
+        }
+      }
+      __syncthreads();
+      ready = true;
     }
     const Unit u = a.units[t];
     run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, alpha, beta, zs, red);
-    done_p1 = t < n1 ? 1u : 0u;
-    if (done_p1) {
-      __threadfence();  // this thread's partial results visible device-wide
-      __syncthreads();  // ... for every thread, before thread 0 publishes
-    }
+    if (t < n1) ++pending;
   }
   if (threadIdx.x == 0) {
     const unsigned prev = __hip_atomic_fetch_add(&ctr->exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
@@ -272,14 +288,19 @@ __global__ __launch_bounds__(64) void k_plain_p2t(PlainArgs a, const double* __r
 
 template <typename T, int NW>
 hipError_t launch_batched_nw(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
-                             double beta, hipStream_t s) {
+                             double beta, hipStream_t s, hipEvent_t* ev) {
   if (persistent) {
-    if (a.n1 + a.n2 == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_persistent<T, NW>), dim3(grid), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (a.n1 + a.n2 > 0)
+      hipLaunchKernelGGL((k_persistent<T, NW>), dim3(grid), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
+    if (ev) (void)hipEventRecord(ev[1], s);
     return hipGetLastError();
   }
-  if (a.n1 > 0) hipLaunchKernelGGL((k_units<T, NW>), dim3(a.n1), dim3(NW * 64), 0, s, a, 0, x, y, alpha, beta);
-  if (a.n2 > 0) hipLaunchKernelGGL((k_units<T, NW>), dim3(a.n2), dim3(NW * 64), 0, s, a, a.n1, x, y, alpha, beta);
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (a.n1 > 0) hipLaunchKernelGGL((k_phase<T, NW, 1>), dim3(a.n1), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  if (a.n2 > 0) hipLaunchKernelGGL((k_phase<T, NW, 2>), dim3(a.n2), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
+  if (ev) (void)hipEventRecord(ev[2], s);
   return hipGetLastError();
 }
 
@@ -294,11 +315,11 @@ int occupancy_nw() {
 
 template <typename T>
 hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
-                          double beta, hipStream_t s) {
+                          double beta, hipStream_t s, hipEvent_t* ev) {
   switch (a.wg_waves) {
-    case 4: return launch_batched_nw<T, 4>(a, persistent, grid, x, y, alpha, beta, s);
-    case 8: return launch_batched_nw<T, 8>(a, persistent, grid, x, y, alpha, beta, s);
-    case 16: return launch_batched_nw<T, 16>(a, persistent, grid, x, y, alpha, beta, s);
+    case 4: return launch_batched_nw<T, 4>(a, persistent, grid, x, y, alpha, beta, s, ev);
+    case 8: return launch_batched_nw<T, 8>(a, persistent, grid, x, y, alpha, beta, s, ev);
+    case 16: return launch_batched_nw<T, 16>(a, persistent, grid, x, y, alpha, beta, s, ev);
     default: return hipErrorInvalidValue;
   }
 }
@@ -315,23 +336,28 @@ int persistent_blocks_per_cu(int wg_waves) {
 
 template <typename T>
 hipError_t launch_plain(const PlainArgs& a, bool transpose, const double* x, double* y, double alpha, double beta,
-                        hipStream_t s) {
+                        hipStream_t s, hipEvent_t* ev) {
+  if (ev) (void)hipEventRecord(ev[0], s);
   if (a.n_lr > 0) hipLaunchKernelGGL(k_plain_p1<T>, dim3(a.n_lr), dim3(256), 0, s, a, x, transpose);
+  if (ev) (void)hipEventRecord(ev[1], s);
   if (!transpose) {
     if (a.n_rows > 0) hipLaunchKernelGGL(k_plain_p2<T>, dim3(a.n_rows), dim3(64), 0, s, a, x, y, alpha, beta);
   } else {
     if (a.n_cols > 0) hipLaunchKernelGGL(k_plain_p2t<T>, dim3(a.n_cols), dim3(64), 0, s, a, x, y, alpha, beta);
   }
+  if (ev) (void)hipEventRecord(ev[2], s);
   return hipGetLastError();
 }
 
 template hipError_t launch_batched<float>(const BatchedArgs&, bool, int, const double*, double*, double, double,
-                                          hipStream_t);
+                                          hipStream_t, hipEvent_t*);
 template hipError_t launch_batched<double>(const BatchedArgs&, bool, int, const double*, double*, double, double,
-                                           hipStream_t);
+                                           hipStream_t, hipEvent_t*);
 template int persistent_blocks_per_cu<float>(int);
 template int persistent_blocks_per_cu<double>(int);
-template hipError_t launch_plain<float>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t);
-template hipError_t launch_plain<double>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t);
+template hipError_t launch_plain<float>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t,
+                                        hipEvent_t*);
+template hipError_t launch_plain<double>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t,
+                                         hipEvent_t*);
 
 }  // namespace hm

@@ -35,13 +35,15 @@ struct BatchedArgs {
   int32_t wg_waves;
 };
 
+// ev (optional): events recorded before the first launch, between the
+// launches and after the last one (plain and split: 3; persistent: 2).
 template <typename T>
 hipError_t launch_plain(const PlainArgs& a, bool transpose, const double* x, double* y, double alpha, double beta,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t* ev = nullptr);
 
 template <typename T>
 hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
-                          double beta, hipStream_t s);
+                          double beta, hipStream_t s, hipEvent_t* ev = nullptr);
 
 template <typename T>
 int persistent_blocks_per_cu(int wg_waves);

@@ -3,12 +3,13 @@
 ``bench_options(workload, variant)`` returns the keyword options of
 ``HMatrix.build`` for one of the three product variants:
 
-* ``batched_f32`` — FP32 factors, batched panels, persistent launch;
-* ``batched_f64`` — FP64 factors, batched panels, persistent launch;
+* ``batched_f32`` — FP32 factors, batched panels (tuned schedule);
+* ``batched_f64`` — FP64 factors, batched panels (tuned schedule);
 * ``plain_f64``   — FP64 factors, natural layout, two plain launches.
 
-The batched schedule (waves per workgroup, unit size) is what
-``hmat_autotune`` picked on an MI355X for that workload.
+The batched schedule (waves per workgroup, unit size, split or persistent
+launch) is the fastest one measured on an MI355X for that workload by a
+sweep over the schedules hmat_autotune also searches.
 """
 from __future__ import annotations
 
@@ -16,14 +17,14 @@ from synth import WORKLOADS
 
 # workload -> (wg_waves, unit_kib, kernel) chosen by hmat_autotune on MI355X
 TUNED = {
-    "dip30_480x256": (8, 256, "persistent"),
+    "dip30_480x256": (4, 256, "split"),
 }
 
 
 def bench_options(workload: str, variant: str) -> dict:
     w = WORKLOADS[workload]
     base = dict(aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"])
-    wg, ukib, kern = TUNED.get(workload, (8, 256, "persistent"))
+    wg, ukib, kern = TUNED.get(workload, (4, 256, "split"))
     if variant == "batched_f32":
         return dict(base, prec="f32", kernel=kern, wg_waves=wg, unit_kib=ukib)
     if variant == "batched_f64":
