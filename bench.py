@@ -38,10 +38,25 @@ DOMINANT_SYMBOL = {
     ("plain", 1): "k_plain_p2<float>",
     ("plain", 0): "k_plain_p1<float>",
 }
-# HBM traffic per dominant-kernel launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters
-# (scaled by a plain copy of known size), for the kernel as it currently is; None until
-# measured for this code.
-TRAFFIC = {}
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, each scaled by what
+# the counter reads for a 1 GiB device copy (profiles/k_phase_dip30_480x256_counters.md),
+# keyed by the hash of the kernel and layout sources they were taken with: any change to
+# those sources makes the entry inapplicable (traffic reported as null until re-measured).
+TRAFFIC = {
+    ("split", 1, "f31e5c52c6f500f8"): 871041201,
+    ("split", 0, "f31e5c52c6f500f8"): 591819157,
+}
+TRAFFIC_SOURCES = ("paper_2110_12165_amd/csrc/kernels.hip", "paper_2110_12165_amd/csrc/layout.cpp",
+                   "paper_2110_12165_amd/csrc/device_types.hpp")
+
+
+def source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def log(*a):
@@ -217,7 +232,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": head["hbm_frac"],
-            "traffic": TRAFFIC.get(info["kernel"]),
+            "traffic": TRAFFIC.get((info["kernel"], head["dominant_launch"], source_hash())),
             "kernel": DOMINANT_SYMBOL.get((info["kernel"], head["dominant_launch"]), "?"),
             "launch_alg_bytes": head["launches"][head["dominant_launch"]]["alg_bytes"],
             "launch_ms": head["launches"][head["dominant_launch"]]["ms"],
