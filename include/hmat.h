@@ -266,6 +266,45 @@ typedef struct {
 hmat_status rs_rhs(hmat_t A, hmat_t B, const rs_params* p, const double* y, double* dydt,
                    double* V_out, void* stream);
 
+/* State of the adaptive Runge-Kutta integration (host struct, read and
+ * updated by rs_rk45_attempt / rs_rk45_step). */
+typedef struct {
+  double t;                /* simulated time [s] */
+  double dt;               /* step to try next [s] (> 0) */
+  double eps_rk;           /* allowance eps_RK of section 2.2; <= 0 means 1e-4 */
+  double last_err;         /* err / eps_RK of the last attempt */
+  int64_t accepted;        /* accepted steps so far */
+  int64_t rejected;        /* rejected attempts so far */
+} rs_rk45_state;
+
+/* Bytes of device workspace rs_rk45_attempt needs for n elements:
+ * 8 * (28 n + 32).  n < 0 returns -1. */
+int64_t rs_rk45_workspace_bytes(int64_t n);
+
+/*
+ * rs_rk45_attempt — one attempt of the embedded Runge-Kutta 5(4) pair of
+ * Cash & Karp on the 3N ODEs (section 2.2): six right-hand-side evaluations
+ * (rs_rhs: slip rate, products with A and B, eqs. (8), (12)), the largest
+ * relative difference err between the 5th- and 4th-order solutions, and the
+ * step control of eqs. (14)-(15) with r = err / eps_RK (non-finite err:
+ * reject with dt/2).  On acceptance y becomes the 5th-order solution, the
+ * slip D advances by eq. (16), t += dt and accepted += 1; otherwise y and D
+ * are unchanged and rejected += 1.  st->dt becomes the next step.
+ *   y: DEVICE 3n (phi | tau | sigma), updated in place; D: DEVICE n slip.
+ *   workspace: DEVICE, at least rs_rk45_workspace_bytes(n), 8-byte aligned.
+ *   force: -1 let the controller decide; 1 accept / 0 reject regardless of
+ *     err and leave st->dt unchanged (replay of a recorded step sequence).
+ *   Synchronises the stream once (to read err).  Allocates nothing.
+ */
+hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                            rs_rk45_state* st, int32_t force, void* stream);
+
+/* rs_rk45_step — rs_rk45_attempt with the controller deciding, repeated
+ * until one attempt is accepted (HMAT_OK) or max_attempts have been
+ * rejected (HMAT_ESTATE, state kept consistent). */
+hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                         rs_rk45_state* st, int32_t max_attempts, void* stream);
+
 /* Release the handle and all its device memory (NULL is ignored).
  * Synchronises the device first. */
 void hmat_destroy(hmat_t h);

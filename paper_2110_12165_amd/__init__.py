@@ -17,7 +17,7 @@ import numpy as np
 from . import _lib
 from ._lib import HmatError, check
 
-__all__ = ["HMatrix", "rs_rhs", "HmatError", "library"]
+__all__ = ["HMatrix", "rs_rhs", "RK45", "HmatError", "library"]
 
 
 def library():
@@ -201,3 +201,59 @@ def rs_rhs(A: HMatrix, B, y, a, b, dc, V0, f0, eta_rad, V_pl, dydt=None, V_out=N
     check(lib.rs_rhs(A._h, None if B is None else B._h, C.byref(p), _dptr(y), _dptr(out),
                      None if V_out is None else _dptr(V_out), _stream_ptr(stream)))
     return out
+
+
+class RK45:
+    """Adaptive Runge-Kutta 5(4) integration of the rate-and-state ODEs on the
+    GPU (rs_rk45_attempt / rs_rk45_step): the stage combinations, the products
+    with A (and B), the right-hand side, the error estimate and the slip
+    update all run in the library; the step control of eqs. (14)-(15) is
+    applied after each attempt."""
+
+    def __init__(self, A, B, a, b, dc, V0, f0, eta_rad, V_pl, eps_rk=1e-4, dt0=1.0):
+        torch = _torch()
+        self.A, self.B = A, B
+        n = A.n
+        for t in (a, b, dc):
+            if t.shape != (n,) or t.dtype != torch.float64 or not t.is_cuda:
+                raise ValueError("a, b, dc must be float64 GPU tensors of length n")
+        self._keep = (a, b, dc)
+        self.params = _lib.RsParams(n, V0, f0, eta_rad, V_pl, a.data_ptr(), b.data_ptr(), dc.data_ptr())
+        nbytes = _lib.load().rs_rk45_workspace_bytes(n)
+        self.workspace = torch.empty(nbytes // 8, dtype=torch.float64, device=a.device)
+        self.state = _lib.RsRk45State(0.0, dt0, eps_rk, 0.0, 0, 0)
+
+    def _check(self, y, D):
+        torch = _torch()
+        n = self.A.n
+        if y.shape != (3 * n,) or D.shape != (n,) or y.dtype != torch.float64 or D.dtype != torch.float64:
+            raise ValueError("y must be (3n,) and D (n,) float64 GPU tensors")
+        if not (y.is_contiguous() and D.is_contiguous()):
+            raise ValueError("y and D must be contiguous")
+
+    def attempt(self, y, D, force=-1, stream=None):
+        self._check(y, D)
+        lib = _lib.load()
+        check(lib.rs_rk45_attempt(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
+                                  _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), force,
+                                  _stream_ptr(stream)))
+        return self.state.last_err
+
+    def step(self, y, D, max_attempts=64, stream=None):
+        self._check(y, D)
+        lib = _lib.load()
+        check(lib.rs_rk45_step(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
+                               _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), max_attempts,
+                               _stream_ptr(stream)))
+
+    @property
+    def t(self):
+        return self.state.t
+
+    @property
+    def dt(self):
+        return self.state.dt
+
+    @dt.setter
+    def dt(self, v):
+        self.state.dt = v

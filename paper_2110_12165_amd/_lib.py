@@ -54,6 +54,11 @@ class RsParams(C.Structure):
                 ("V_pl", C.c_double), ("a", C.c_void_p), ("b", C.c_void_p), ("dc", C.c_void_p)]
 
 
+class RsRk45State(C.Structure):
+    _fields_ = [("t", C.c_double), ("dt", C.c_double), ("eps_rk", C.c_double), ("last_err", C.c_double),
+                ("accepted", C.c_int64), ("rejected", C.c_int64)]
+
+
 # Symbols declared in include/hmat.h, with their ctypes signatures.
 SIGNATURES = {
     "hmat_default_opts": (None, [C.POINTER(HmatOpts)]),
@@ -72,6 +77,11 @@ SIGNATURES = {
     "hmat_profile": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(HmatProfile)]),
     "rs_rhs": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
                          C.c_void_p]),
+    "rs_rk45_workspace_bytes": (C.c_int64, [C.c_int64]),
+    "rs_rk45_attempt": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.POINTER(RsRk45State), C.c_int32, C.c_void_p]),
+    "rs_rk45_step": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.POINTER(RsRk45State), C.c_int32, C.c_void_p]),
     "hmat_destroy": (None, [C.c_void_p]),
     "hmat_last_error": (C.c_char_p, []),
 }

@@ -523,6 +523,85 @@ hmat_status rs_rhs(hmat_t A, hmat_t B, const rs_params* p, const double* y, doub
   });
 }
 
+int64_t rs_rk45_workspace_bytes(int64_t n) { return n < 0 ? -1 : 8 * (28 * n + 32); }
+
+hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                            rs_rk45_state* st, int32_t force, void* stream) {
+  return guarded([&] {
+    if (!A || !p || !y || !D || !workspace || !st) hm::fail(HMAT_EINVAL, "null argument");
+    if (!A->on_device || (B && !B->on_device)) hm::fail(HMAT_ESTATE, "handle holds host blocks only");
+    if (p->n != A->H.n || (B && B->H.n != A->H.n)) hm::fail(HMAT_EINVAL, "n does not match the handles");
+    if (B && B->device != A->device) hm::fail(HMAT_EINVAL, "A and B live on different devices");
+    if (!p->a || !p->b || !p->dc) hm::fail(HMAT_EINVAL, "null friction parameter array");
+    if (!(p->V0 > 0.0) || !(p->eta_rad >= 0.0) || !std::isfinite(p->f0) || !std::isfinite(p->V_pl))
+      hm::fail(HMAT_EINVAL, "bad friction constants");
+    if (!(st->dt > 0.0) || !std::isfinite(st->dt)) hm::fail(HMAT_EINVAL, "dt must be positive and finite");
+    if (force < -1 || force > 1) hm::fail(HMAT_EINVAL, "force must be -1, 0 or 1");
+    if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
+    DeviceGuard g(A->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A->H.n, n3 = 3 * n;
+    double* ws = static_cast<double*>(workspace);
+    double* k = ws;                 // 6 * n3
+    double* ys = k + 6 * n3;        // n3
+    double* y5 = ys + n3;           // n3
+    double* Vs = y5 + n3;           // n
+    double* xv = Vs + n;            // n
+    double* ax = xv + n;            // n
+    double* bx = ax + n;            // n
+    auto* err_bits = reinterpret_cast<unsigned long long*>(bx + n);
+    const double dt = st->dt;
+    for (int stage = 0; stage < 6; ++stage) {
+      const double* yin = y;
+      if (stage > 0) {
+        check_hip(hm::launch_rk_stage(n3, stage, dt, y, k, ys, s), "stage launch");
+        yin = ys;
+      }
+      check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, yin, xv, stage == 0 ? Vs : nullptr, s),
+                "slip-rate launch");
+      check_hip(A->product(false, xv, ax, 1.0, 0.0, s, A->kernel), "product launch");
+      if (B) check_hip(B->product(false, xv, bx, 1.0, 0.0, s, B->kernel), "product launch");
+      check_hip(hm::launch_rs_rhs(n, *p, yin, ax, B ? bx : nullptr, k + stage * n3, s), "rhs launch");
+    }
+    check_hip(hm::launch_rk_finish(n3, dt, y, k, y5, err_bits, s), "error launch");
+    unsigned long long bits = 0;
+    check_hip(hipMemcpyAsync(&bits, err_bits, sizeof(bits), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    double err;
+    std::memcpy(&err, &bits, sizeof(err));
+    const double eps = st->eps_rk > 0.0 ? st->eps_rk : 1e-4;
+    const double r = err / eps;
+    st->last_err = r;
+    const bool finite = std::isfinite(r);
+    const bool ok = force >= 0 ? force == 1 : (finite && r <= 1.0);
+    if (ok) {
+      check_hip(hm::launch_rk_accept(n, dt, p->V0, p->a, y5, Vs, y, D, s), "accept launch");
+      st->t += dt;
+      ++st->accepted;
+    } else {
+      ++st->rejected;
+    }
+    if (force < 0) {  // eqs. (14)-(15)
+      if (!finite) st->dt = 0.5 * dt;
+      else if (ok) st->dt = r == 0.0 ? 2.0 * dt : std::min(2.0 * dt, 0.9 * dt * std::pow(r, -0.2));
+      else st->dt = std::max(0.5 * dt, 0.9 * dt * std::pow(r, -0.25));
+    }
+  });
+}
+
+hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                         rs_rk45_state* st, int32_t max_attempts, void* stream) {
+  if (max_attempts < 1) return set_err(HMAT_EINVAL, "max_attempts must be >= 1");
+  if (!st) return set_err(HMAT_EINVAL, "null argument");
+  const int64_t acc0 = st->accepted;
+  for (int32_t k = 0; k < max_attempts; ++k) {
+    const hmat_status rc = rs_rk45_attempt(A, B, p, y, D, workspace, st, -1, stream);
+    if (rc != HMAT_OK) return rc;
+    if (st->accepted > acc0) return HMAT_OK;
+  }
+  return set_err(HMAT_ESTATE, "no attempt accepted within max_attempts");
+}
+
 void hmat_destroy(hmat_t h) { delete h; }
 
 const char* hmat_last_error(void) { return g_err.c_str(); }

@@ -55,7 +55,107 @@ __global__ void k_rhs(int64_t n, double V0, double f0, double eta, const double*
   dydt[2 * n + i] = dsig;
 }
 
+// ---------------------------------------------------------------------------
+// Embedded Runge-Kutta 5(4) of Cash & Karp (1990): stage combinations, the
+// relative difference of the two solutions (section 2.2) and the accepted
+// update with the trapezoidal slip rule of eq. (16).
+// ---------------------------------------------------------------------------
+__constant__ double kA[6][5] = {
+    {0, 0, 0, 0, 0},
+    {1.0 / 5.0, 0, 0, 0, 0},
+    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0},
+    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0},
+    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0},
+    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
+__constant__ double kB5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
+__constant__ double kB4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0, 0.25};
+
+// ys = y + dt * sum_{j<s} a_sj k_j
+__global__ void k_stage(int64_t n3, int s, double dt, const double* __restrict__ y, const double* __restrict__ k,
+                        double* __restrict__ ys) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n3) return;
+  double v = y[i];
+  for (int j = 0; j < s; ++j) {
+    const double c = kA[s][j];
+    if (c != 0.0) v = v + (dt * c) * k[j * n3 + i];
+  }
+  ys[i] = v;
+}
+
+__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+
+// y5, and max_i |y5 - y4| / max(|y5|, 1e-300) (non-negative doubles order like
+// their bit patterns, so the maximum is an integer atomic max; NaN wins).
+__global__ __launch_bounds__(256) void k_finish(int64_t n3, double dt, const double* __restrict__ y,
+                                                const double* __restrict__ k, double* __restrict__ y5,
+                                                unsigned long long* err_bits) {
+  __shared__ double part[4];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double e = 0.0;
+  if (i < n3) {
+    double v5 = y[i], v4 = y[i];
+    for (int j = 0; j < 6; ++j) {
+      const double kj = k[j * n3 + i];
+      if (kB5[j] != 0.0) v5 = v5 + (dt * kB5[j]) * kj;
+      if (kB4[j] != 0.0) v4 = v4 + (dt * kB4[j]) * kj;
+    }
+    y5[i] = v5;
+    e = fabs(v5 - v4) / fmax(fabs(v5), 1e-300);
+    if (e != e) e = __longlong_as_double(0x7ff8000000000000ll);
+  }
+  for (int d = 32; d >= 1; d >>= 1) {
+    const double o = __shfl_xor(e, d, 64);
+    e = (o != o || o > e) ? o : e;
+  }
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (lane == 0) part[wave] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = part[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = (part[w] != part[w] || part[w] > m) ? part[w] : m;
+    atomicMax(err_bits, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+// accepted step: D += dt/2 (V(y) + V(y5)) (eq. 16); y = y5
+__global__ void k_accept(int64_t n, double dt, double V0, const double* __restrict__ a, const double* __restrict__ y5,
+                         const double* __restrict__ Vstart, double* __restrict__ y, double* __restrict__ D) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const double phi = y5[i], tau = y5[n + i], sig = y5[2 * n + i];
+  const double ai = a[i];
+  const double q = tau / (ai * sig), e = phi / ai;
+  const double V1 = V0 * (exp(q - e) - exp(-q - e));
+  D[i] = D[i] + 0.5 * dt * (Vstart[i] + V1);
+  y[i] = phi;
+  y[n + i] = tau;
+  y[2 * n + i] = sig;
+}
+
 }  // namespace
+
+hipError_t launch_rk_stage(int64_t n3, int s, double dt, const double* y, const double* k, double* ys,
+                           hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_stage, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, st, n3, s, dt, y, k, ys);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk_finish(int64_t n3, double dt, const double* y, const double* k, double* y5,
+                            unsigned long long* err_bits, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, err_bits);
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, st, n3, dt, y, k, y5, err_bits);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk_accept(int64_t n, double dt, double V0, const double* a, const double* y5, const double* Vstart,
+                            double* y, double* D, hipStream_t st) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, n, dt, V0, a, y5, Vstart, y, D);
+  return hipGetLastError();
+}
 
 hipError_t launch_rs_slip_rate(int64_t n, double V0, double V_pl, const double* a, const double* y, double* x,
                                double* V_out, hipStream_t s) {

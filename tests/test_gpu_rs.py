@@ -1,0 +1,121 @@
+"""GPU parity of the rate-and-state right-hand side and of the RK45 step
+(section 2.2, eqs. 7-16) against the FP64 oracle, on shared H-matrix factors.
+
+Tolerances: the right-hand side combines the product (shared factors, FP64:
+<= 1e-13 relative) with element-wise exp/sinh/cosh evaluated by the GPU's
+math library (a few ulp): components are compared against 1e-10 of the
+largest magnitude of that component.  RK45 in replay mode (same dt and
+decisions as the oracle) compounds such differences over the steps:
+state and slip within 1e-8 relative after 40 steps.
+"""
+import numpy as np
+import pytest
+
+from _util import oracle_blocks, say
+from oracle import friction as fr
+from oracle import rk45
+from oracle.greens import CoplanarRectGeometry
+from oracle.hmatrix import HMatrix as OracleH
+from synth import WORKLOADS, config_fault, friction_params, loguniform_rates
+from synth.faults import MU, NU
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def case():
+    import torch
+
+    import paper_2110_12165_amd as hm
+    name = "planar64x32"
+    w = WORKLOADS[name]
+    f = config_fault(name)
+    g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
+    H = OracleH.build(g, w["leaf"], w["eta"], w["aca_eps"], w["lattice"])
+    p = friction_params(f)
+    Bk = oracle_blocks(H)
+    dev = torch.device("cuda:0")
+    Hg = hm.HMatrix.from_blocks(Bk["n"], Bk["perm"], Bk["desc"], Bk["off"], Bk["values"], prec="f64",
+                                kernel="split")
+    dp = {k: torch.tensor(p[k], device=dev) for k in ("a", "b", "dc")}
+    return torch, hm, f, H, p, Hg, dp, dev
+
+
+def _state(f, p, seed):
+    V = loguniform_rates(f.n, seed)
+    return fr.initial_state(V, p, p["sigma"])
+
+
+def test_rs_rhs_parity(case):
+    torch, hm, f, H, p, Hg, dp, dev = case
+    say("[rs_rhs] planar64x32")
+    for seed in (0, 1):
+        y = _state(f, p, seed)
+        ref, Vref = fr.rhs(y, p, H.matvec)
+        V = torch.empty(f.n, dtype=torch.float64, device=dev)
+        got = hm.rs_rhs(Hg, None, torch.tensor(y, device=dev), dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"],
+                        p["eta_rad"], p["V_pl"], V_out=V).cpu().numpy()
+        n = f.n
+        for c in range(3):
+            sl = slice(c * n, (c + 1) * n)
+            scale = max(np.max(np.abs(ref[sl])), 1e-300)
+            assert np.max(np.abs(got[sl] - ref[sl])) <= 1e-10 * scale, c
+        np.testing.assert_allclose(V.cpu().numpy(), Vref, rtol=1e-12)
+
+
+def test_rk45_replay_parity(case):
+    torch, hm, f, H, p, Hg, dp, dev = case
+    say("[rk45 replay] planar64x32, 40 steps")
+    y0 = _state(f, p, 0)
+    out = rk45.integrate(lambda y: fr.rhs(y, p, H.matvec), y0, 1.0, 40,
+                         slip_rate=lambda y: fr.slip_rate(y[:f.n], y[f.n:2 * f.n], y[2 * f.n:], p["a"], p["V0"]))
+    rk = hm.RK45(Hg, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for t, dt, r, ok in out["log"]:
+        rk.dt = dt
+        r_gpu = rk.attempt(y, D, force=1 if ok else 0)
+        assert r_gpu == pytest.approx(r, rel=1e-6, abs=1e-12)
+    assert rk.state.accepted == 40
+    assert rk.t == pytest.approx(out["t"], rel=1e-14)
+    yg, Dg = y.cpu().numpy(), D.cpu().numpy()
+    n = f.n
+    for c in range(3):
+        sl = slice(c * n, (c + 1) * n)
+        assert np.max(np.abs(yg[sl] - out["y"][sl])) <= 1e-8 * np.max(np.abs(out["y"][sl]))
+    assert np.max(np.abs(Dg - out["D"])) <= 1e-8 * np.max(np.abs(out["D"]))
+
+
+def test_rk45_free_running_matches_controller(case):
+    torch, hm, f, H, p, Hg, dp, dev = case
+    say("[rk45 free] planar64x32, 25 steps")
+    y0 = _state(f, p, 1)
+    out = rk45.integrate(lambda y: fr.rhs(y, p, H.matvec), y0, 1.0, 25)
+    rk = hm.RK45(Hg, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    gpu_log = []
+    while rk.state.accepted < 25:
+        dt = rk.dt
+        acc0 = rk.state.accepted
+        r = rk.attempt(y, D)
+        gpu_log.append((dt, r, rk.state.accepted > acc0))
+    assert len(gpu_log) == len(out["log"])
+    for (dt, r, ok), (_, dto, ro, oko) in zip(gpu_log, out["log"]):
+        assert ok == oko
+        assert dt == pytest.approx(dto, rel=1e-9)
+        assert r == pytest.approx(ro, rel=1e-5, abs=1e-12)
+
+
+def test_plate_rate_state_stays_put(case):
+    torch, hm, f, H, p, Hg, dp, dev = case
+    y0 = fr.initial_state(p["V_pl"], p, p["sigma"])
+    rk = hm.RK45(Hg, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"], dt0=1e3)
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    for _ in range(10):
+        rk.step(y, D)
+    yg = y.cpu().numpy()
+    np.testing.assert_allclose(yg, y0, rtol=1e-12)
+    # slip grows at the plate rate
+    np.testing.assert_allclose(D.cpu().numpy(), p["V_pl"] * rk.t, rtol=1e-9)

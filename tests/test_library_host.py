@@ -28,7 +28,7 @@ def lib():
 def _declared_functions():
     src = open(os.path.join(ROOT, "include", "hmat.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"^\s*(?:hmat_status|void|const char\*)\s+(\w+)\s*\(", src, flags=re.M)))
+    return sorted(set(re.findall(r"^\s*(?:hmat_status|void|const char\*|int64_t)\s+(\w+)\s*\(", src, flags=re.M)))
 
 
 def test_exports_every_declared_symbol(lib):
