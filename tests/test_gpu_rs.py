@@ -41,16 +41,22 @@ def case():
     return torch, hm, f, H, p, Hg, dp, dev
 
 
-def _state(f, p, seed):
+def _state(f, p, seed, kick=0.0):
+    """Steady state at log-uniform slip rates; kick != 0 moves the state
+    variable off steady state by U(-kick, kick) so that dphi/dt is not a
+    difference of equal terms."""
     V = loguniform_rates(f.n, seed)
-    return fr.initial_state(V, p, p["sigma"])
+    y = fr.initial_state(V, p, p["sigma"])
+    if kick:
+        y[:f.n] += np.random.default_rng(100 + seed).uniform(-kick, kick, f.n)
+    return y
 
 
 def test_rs_rhs_parity(case):
     torch, hm, f, H, p, Hg, dp, dev = case
     say("[rs_rhs] planar64x32")
     for seed in (0, 1):
-        y = _state(f, p, seed)
+        y = _state(f, p, seed, kick=0.05)
         ref, Vref = fr.rhs(y, p, H.matvec)
         V = torch.empty(f.n, dtype=torch.float64, device=dev)
         got = hm.rs_rhs(Hg, None, torch.tensor(y, device=dev), dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"],
