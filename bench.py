@@ -135,6 +135,48 @@ def cpu_baseline(f, w, x, y_gpu):
     }
 
 
+def rk45_run(torch, hm, f, w, x_np, n_steps):
+    """Quasi-dynamic rate-and-state simulation on the benchmark fault with the
+    FP32 batched product: adaptive RK45 with the step control on the GPU,
+    attempts replayed from a HIP graph on a side stream."""
+    from paper_2110_12165_amd.tuning import bench_options
+    from synth import friction_params
+    from synth.faults import MU, NU
+
+    p = friction_params(f)
+    dev = torch.device("cuda:0")
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, **bench_options(WORKLOAD, "batched_f32"))
+    a, b, dc = (torch.tensor(p[k], device=dev) for k in ("a", "b", "dc"))
+    # steady state at the log-uniform slip rates of the product benchmark (eqs. 7-8)
+    V = x_np
+    phi = p["f0"] + p["b"] * np.log(p["V0"] / V)
+    tau = p["a"] * p["sigma"] * np.arcsinh(V / (2 * p["V0"]) * np.exp(phi / p["a"]))
+    y = torch.tensor(np.concatenate([phi, tau, p["sigma"]]), device=dev)
+    D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    rk = hm.RK45(H, None, a, b, dc, p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rk.run(y, D, 2, use_graph=True, stream=s)          # capture + warm-up
+        s.synchronize()
+        t_sim0, acc0, rej0 = rk.t, rk.state.accepted, rk.state.rejected
+        t0 = time.perf_counter()
+        rk.run(y, D, n_steps, use_graph=True, stream=s)
+        s.synchronize()
+        wall = time.perf_counter() - t0
+    attempts = (rk.state.accepted - acc0) + (rk.state.rejected - rej0)
+    xd = torch.tensor(x_np, device=dev)
+    prof = H.profile(xd, torch.empty_like(xd), reps=20)
+    hmvm = 6 * attempts * prof["ms_product"] * 1e-3
+    H.close()
+    log(f"[bench] rk45: {n_steps} steps, {attempts} attempts in {wall:.3f} s, simulated {rk.t - t_sim0:.3e} s")
+    return {"accepted_steps": n_steps, "attempts": attempts, "wall_s": wall,
+            "steps_per_s": n_steps / wall, "attempts_per_s": attempts / wall,
+            "simulated_s": rk.t - t_sim0, "simulated_s_per_wall_s": (rk.t - t_sim0) / wall,
+            "hmvm_share": hmvm / wall, "dt_last": rk.dt,
+            "note": "Cash-Karp RK45, eps_RK 1e-4, graph-replayed attempts; friction a=0.010, b=0.015/0.005, "
+                    "d_c=0.01 m, sigma=50 MPa, V_pl=1e-9 m/s; start from steady state at the benchmark slip rates"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +184,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="batched_f32,plain_f64,batched_f64")
+    ap.add_argument("--rk-steps", type=int, default=50,
+                    help="accepted RK45 steps of the rate-and-state simulation on the same fault (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -252,6 +296,8 @@ def main():
     if "batched_f64" in outputs:
         ref = outputs["batched_f64"]
         line["rel_diff_f32_vs_f64_gpu"] = float(np.linalg.norm(outputs["batched_f32"] - ref) / np.linalg.norm(ref))
+    if args.rk_steps > 0:
+        line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
         line["cpu_baseline"] = cpu_baseline(f, w, x_np, outputs["batched_f32"])

@@ -284,24 +284,37 @@ int64_t rs_rk45_workspace_bytes(int64_t n);
 /*
  * rs_rk45_attempt — one attempt of the embedded Runge-Kutta 5(4) pair of
  * Cash & Karp on the 3N ODEs (section 2.2): six right-hand-side evaluations
- * (rs_rhs: slip rate, products with A and B, eqs. (8), (12)), the largest
+ * (slip rate of eq. (7), products with A and B, eqs. (8), (12)), the largest
  * relative difference err between the 5th- and 4th-order solutions, and the
  * step control of eqs. (14)-(15) with r = err / eps_RK (non-finite err:
  * reject with dt/2).  On acceptance y becomes the 5th-order solution, the
  * slip D advances by eq. (16), t += dt and accepted += 1; otherwise y and D
  * are unchanged and rejected += 1.  st->dt becomes the next step.
  *   y: DEVICE 3n (phi | tau | sigma), updated in place; D: DEVICE n slip.
- *   workspace: DEVICE, at least rs_rk45_workspace_bytes(n), 8-byte aligned.
+ *   workspace: DEVICE, at least rs_rk45_workspace_bytes(n), 8-byte aligned;
+ *     it also holds the device copy of the integration state.
  *   force: -1 let the controller decide; 1 accept / 0 reject regardless of
  *     err and leave st->dt unchanged (replay of a recorded step sequence).
- *   Synchronises the stream once (to read err).  Allocates nothing.
+ *   Synchronises the stream (state copied in and out).  Allocates nothing.
  */
 hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                             rs_rk45_state* st, int32_t force, void* stream);
 
-/* rs_rk45_step — rs_rk45_attempt with the controller deciding, repeated
- * until one attempt is accepted (HMAT_OK) or max_attempts have been
- * rejected (HMAT_ESTATE, state kept consistent). */
+/*
+ * rs_rk45_run — advance until n_accept more steps are accepted.  The step
+ * control runs on the GPU (the state lives in the workspace), so attempts
+ * are enqueued back to back with no host round trip; the host reads the
+ * state once per batch (a batch is as many attempts as steps still missing;
+ * attempts after the target is reached change nothing).  use_graph != 0 and
+ * a non-null stream: one attempt is captured once as a HIP graph (cached in
+ * A, re-captured when any argument changes) and replayed.
+ * max_attempts > 0 bounds the attempts (HMAT_ESTATE if the target is not
+ * reached; the state stays consistent).  st is updated on return.
+ */
+hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                        rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, int32_t use_graph, void* stream);
+
+/* rs_rk45_step — rs_rk45_run for one accepted step, without a graph. */
 hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                          rs_rk45_state* st, int32_t max_attempts, void* stream);
 

@@ -246,6 +246,15 @@ class RK45:
                                _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), max_attempts,
                                _stream_ptr(stream)))
 
+    def run(self, y, D, n_accept, max_attempts=0, use_graph=True, stream=None):
+        """Advance n_accept accepted steps with the step control on the GPU
+        (rs_rk45_run).  The graph path needs a non-default stream."""
+        self._check(y, D)
+        lib = _lib.load()
+        check(lib.rs_rk45_run(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
+                              _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), n_accept,
+                              max_attempts, 1 if use_graph else 0, _stream_ptr(stream)))
+
     @property
     def t(self):
         return self.state.t

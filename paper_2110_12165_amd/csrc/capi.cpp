@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdint>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -77,10 +78,49 @@ struct hmat_s {
   double* rs_ax = nullptr;  // n doubles: A (V - V_pl)
   double* rs_bx = nullptr;  // n doubles: B (V - V_pl)
   hmat_stats st{};
+  // captured Runge-Kutta attempt (rs_rk45_run), keyed by everything it reads
+  hipGraph_t rk_graph_g = nullptr;
+  hipGraphExec_t rk_exec = nullptr;
+  std::vector<const void*> rk_key;
+
+  template <typename F>
+  void rk_graph(hmat_t B, const rs_params* p, const double* y, const double* D, const void* ws, hipStream_t s,
+                F&& enqueue) {
+    std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, ws, s};
+    const double consts[4] = {p->V0, p->f0, p->eta_rad, p->V_pl};
+    for (double c : consts) {
+      const void* v;
+      std::memcpy(&v, &c, sizeof(v));
+      key.push_back(v);
+    }
+    if (rk_exec && key == rk_key) return;
+    drop_graph();
+    check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      enqueue(s);
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(s, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    check_hip(hipStreamEndCapture(s, &rk_graph_g), "hipStreamEndCapture");
+    check_hip(hipGraphInstantiate(&rk_exec, rk_graph_g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    rk_key = key;
+  }
+
+  void drop_graph() {
+    if (rk_exec) (void)hipGraphExecDestroy(rk_exec);
+    if (rk_graph_g) (void)hipGraphDestroy(rk_graph_g);
+    rk_exec = nullptr;
+    rk_graph_g = nullptr;
+    rk_key.clear();
+  }
 
   ~hmat_s() {
     if (!on_device) return;
     (void)hipDeviceSynchronize();
+    drop_graph();
     for (void* p : batched_allocs) (void)hipFree(p);
     for (void* p : allocs) (void)hipFree(p);
   }
@@ -109,6 +149,7 @@ struct hmat_s {
 
   void drop_batched() {
     (void)hipDeviceSynchronize();
+    drop_graph();
     for (void* p : batched_allocs) (void)hipFree(p);
     batched_allocs.clear();
     bytes_batched = 0;
@@ -525,81 +566,135 @@ hmat_status rs_rhs(hmat_t A, hmat_t B, const rs_params* p, const double* y, doub
 
 int64_t rs_rk45_workspace_bytes(int64_t n) { return n < 0 ? -1 : 8 * (28 * n + 32); }
 
+namespace {
+
+struct RkWs {
+  double *k, *ys, *y5, *Vs, *xv, *ax, *bx;
+  hm::RkDevState* st;
+};
+
+RkWs rk_workspace(void* workspace, int64_t n) {
+  RkWs w;
+  double* base = static_cast<double*>(workspace);
+  w.k = base;
+  w.ys = w.k + 18 * n;
+  w.y5 = w.ys + 3 * n;
+  w.Vs = w.y5 + 3 * n;
+  w.xv = w.Vs + n;
+  w.ax = w.xv + n;
+  w.bx = w.ax + n;
+  w.st = reinterpret_cast<hm::RkDevState*>(w.bx + n);
+  return w;
+}
+
+void check_rk_args(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                   const rs_rk45_state* st) {
+  static_assert(sizeof(hm::RkDevState) <= 32 * sizeof(double), "device state must fit the workspace tail");
+  if (!A || !p || !y || !D || !workspace || !st) hm::fail(HMAT_EINVAL, "null argument");
+  if (!A->on_device || (B && !B->on_device)) hm::fail(HMAT_ESTATE, "handle holds host blocks only");
+  if (p->n != A->H.n || (B && B->H.n != A->H.n)) hm::fail(HMAT_EINVAL, "n does not match the handles");
+  if (B && B->device != A->device) hm::fail(HMAT_EINVAL, "A and B live on different devices");
+  if (!p->a || !p->b || !p->dc) hm::fail(HMAT_EINVAL, "null friction parameter array");
+  if (!(p->V0 > 0.0) || !(p->eta_rad >= 0.0) || !std::isfinite(p->f0) || !std::isfinite(p->V_pl))
+    hm::fail(HMAT_EINVAL, "bad friction constants");
+  if (!(st->dt > 0.0) || !std::isfinite(st->dt)) hm::fail(HMAT_EINVAL, "dt must be positive and finite");
+  if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
+}
+
+// Enqueue one attempt: every kernel reads the step from the device state.
+void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const RkWs& w, hipStream_t s) {
+  const int64_t n = A->H.n, n3 = 3 * n;
+  check_hip(hm::launch_rk_begin(w.st, s), "rk begin launch");
+  for (int stage = 0; stage < 6; ++stage) {
+    const double* yin = y;
+    if (stage > 0) {
+      check_hip(hm::launch_rk_stage(n3, stage, w.st, y, w.k, w.ys, s), "stage launch");
+      yin = w.ys;
+    }
+    check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, yin, w.xv, stage == 0 ? w.Vs : nullptr, s),
+              "slip-rate launch");
+    check_hip(A->product(false, w.xv, w.ax, 1.0, 0.0, s, A->kernel), "product launch");
+    if (B) check_hip(B->product(false, w.xv, w.bx, 1.0, 0.0, s, B->kernel), "product launch");
+    check_hip(hm::launch_rs_rhs(n, *p, yin, w.ax, B ? w.bx : nullptr, w.k + stage * n3, s), "rhs launch");
+  }
+  check_hip(hm::launch_rk_finish_control(n3, w.st, y, w.k, w.y5, s), "error launch");
+  check_hip(hm::launch_rk_accept(n, w.st, p->V0, p->a, w.y5, w.Vs, y, D, s), "accept launch");
+}
+
+void put_state(const RkWs& w, const rs_rk45_state* st, long long target, int force, hipStream_t s) {
+  hm::RkDevState d{};
+  d.t = st->t;
+  d.dt = st->dt;
+  d.eps = st->eps_rk > 0.0 ? st->eps_rk : 1e-4;
+  d.accepted = st->accepted;
+  d.rejected = st->rejected;
+  d.target = target;
+  d.force = force;
+  check_hip(hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+}
+
+void get_state(const RkWs& w, rs_rk45_state* st, hipStream_t s) {
+  hm::RkDevState d{};
+  check_hip(hipMemcpyAsync(&d, w.st, sizeof(d), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+  check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  st->t = d.t;
+  st->dt = d.dt;
+  st->last_err = d.r;
+  st->accepted = d.accepted;
+  st->rejected = d.rejected;
+}
+
+}  // namespace
+
 hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                             rs_rk45_state* st, int32_t force, void* stream) {
   return guarded([&] {
-    if (!A || !p || !y || !D || !workspace || !st) hm::fail(HMAT_EINVAL, "null argument");
-    if (!A->on_device || (B && !B->on_device)) hm::fail(HMAT_ESTATE, "handle holds host blocks only");
-    if (p->n != A->H.n || (B && B->H.n != A->H.n)) hm::fail(HMAT_EINVAL, "n does not match the handles");
-    if (B && B->device != A->device) hm::fail(HMAT_EINVAL, "A and B live on different devices");
-    if (!p->a || !p->b || !p->dc) hm::fail(HMAT_EINVAL, "null friction parameter array");
-    if (!(p->V0 > 0.0) || !(p->eta_rad >= 0.0) || !std::isfinite(p->f0) || !std::isfinite(p->V_pl))
-      hm::fail(HMAT_EINVAL, "bad friction constants");
-    if (!(st->dt > 0.0) || !std::isfinite(st->dt)) hm::fail(HMAT_EINVAL, "dt must be positive and finite");
+    check_rk_args(A, B, p, y, D, workspace, st);
     if (force < -1 || force > 1) hm::fail(HMAT_EINVAL, "force must be -1, 0 or 1");
-    if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
     DeviceGuard g(A->device);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t n = A->H.n, n3 = 3 * n;
-    double* ws = static_cast<double*>(workspace);
-    double* k = ws;                 // 6 * n3
-    double* ys = k + 6 * n3;        // n3
-    double* y5 = ys + n3;           // n3
-    double* Vs = y5 + n3;           // n
-    double* xv = Vs + n;            // n
-    double* ax = xv + n;            // n
-    double* bx = ax + n;            // n
-    auto* err_bits = reinterpret_cast<unsigned long long*>(bx + n);
-    const double dt = st->dt;
-    for (int stage = 0; stage < 6; ++stage) {
-      const double* yin = y;
-      if (stage > 0) {
-        check_hip(hm::launch_rk_stage(n3, stage, dt, y, k, ys, s), "stage launch");
-        yin = ys;
+    const RkWs w = rk_workspace(workspace, A->H.n);
+    put_state(w, st, st->accepted + 1, force, s);
+    enqueue_attempt(A, B, p, y, D, w, s);
+    get_state(w, st, s);
+  });
+}
+
+hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                        rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, int32_t use_graph, void* stream) {
+  return guarded([&] {
+    check_rk_args(A, B, p, y, D, workspace, st);
+    if (n_accept < 0 || max_attempts < 0) hm::fail(HMAT_EINVAL, "counts must be >= 0");
+    if (n_accept == 0) return;
+    DeviceGuard g(A->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const RkWs w = rk_workspace(workspace, A->H.n);
+    const long long target = st->accepted + n_accept;
+    put_state(w, st, target, -1, s);
+    const bool graph = use_graph && s != nullptr;
+    if (graph) A->rk_graph(B, p, y, D, workspace, s, [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, cs); });
+    int64_t launched = 0;
+    for (;;) {
+      int64_t batch = target - st->accepted;
+      if (max_attempts > 0) batch = std::min(batch, max_attempts - launched);
+      if (batch <= 0) break;
+      for (int64_t k = 0; k < batch; ++k) {
+        if (graph) check_hip(hipGraphLaunch(A->rk_exec, s), "hipGraphLaunch");
+        else enqueue_attempt(A, B, p, y, D, w, s);
       }
-      check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, yin, xv, stage == 0 ? Vs : nullptr, s),
-                "slip-rate launch");
-      check_hip(A->product(false, xv, ax, 1.0, 0.0, s, A->kernel), "product launch");
-      if (B) check_hip(B->product(false, xv, bx, 1.0, 0.0, s, B->kernel), "product launch");
-      check_hip(hm::launch_rs_rhs(n, *p, yin, ax, B ? bx : nullptr, k + stage * n3, s), "rhs launch");
+      launched += batch;
+      get_state(w, st, s);
+      if (st->accepted >= target) break;
     }
-    check_hip(hm::launch_rk_finish(n3, dt, y, k, y5, err_bits, s), "error launch");
-    unsigned long long bits = 0;
-    check_hip(hipMemcpyAsync(&bits, err_bits, sizeof(bits), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
-    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
-    double err;
-    std::memcpy(&err, &bits, sizeof(err));
-    const double eps = st->eps_rk > 0.0 ? st->eps_rk : 1e-4;
-    const double r = err / eps;
-    st->last_err = r;
-    const bool finite = std::isfinite(r);
-    const bool ok = force >= 0 ? force == 1 : (finite && r <= 1.0);
-    if (ok) {
-      check_hip(hm::launch_rk_accept(n, dt, p->V0, p->a, y5, Vs, y, D, s), "accept launch");
-      st->t += dt;
-      ++st->accepted;
-    } else {
-      ++st->rejected;
-    }
-    if (force < 0) {  // eqs. (14)-(15)
-      if (!finite) st->dt = 0.5 * dt;
-      else if (ok) st->dt = r == 0.0 ? 2.0 * dt : std::min(2.0 * dt, 0.9 * dt * std::pow(r, -0.2));
-      else st->dt = std::max(0.5 * dt, 0.9 * dt * std::pow(r, -0.25));
-    }
+    if (st->accepted < target) hm::fail(HMAT_ESTATE, "target not reached within max_attempts");
   });
 }
 
 hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                          rs_rk45_state* st, int32_t max_attempts, void* stream) {
   if (max_attempts < 1) return set_err(HMAT_EINVAL, "max_attempts must be >= 1");
-  if (!st) return set_err(HMAT_EINVAL, "null argument");
-  const int64_t acc0 = st->accepted;
-  for (int32_t k = 0; k < max_attempts; ++k) {
-    const hmat_status rc = rs_rk45_attempt(A, B, p, y, D, workspace, st, -1, stream);
-    if (rc != HMAT_OK) return rc;
-    if (st->accepted > acc0) return HMAT_OK;
-  }
-  return set_err(HMAT_ESTATE, "no attempt accepted within max_attempts");
+  return rs_rk45_run(A, B, p, y, D, workspace, st, 1, max_attempts, 0, stream);
 }
 
 void hmat_destroy(hmat_t h) { delete h; }

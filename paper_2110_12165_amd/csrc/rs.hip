@@ -15,6 +15,7 @@
 //             / (1 + eta dV/dtau)
 // The backslip loading tau_dot = -V_pl sum_j A_ij is folded into the product
 // by applying A to V - V_pl.
+#include "device_types.hpp"
 #include "rs.hpp"
 
 namespace hm {
@@ -71,10 +72,11 @@ __constant__ double kB5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0
 __constant__ double kB4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0, 0.25};
 
 // ys = y + dt * sum_{j<s} a_sj k_j
-__global__ void k_stage(int64_t n3, int s, double dt, const double* __restrict__ y, const double* __restrict__ k,
-                        double* __restrict__ ys) {
+__global__ void k_stage(int64_t n3, int s, const RkDevState* __restrict__ st, const double* __restrict__ y,
+                        const double* __restrict__ k, double* __restrict__ ys) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n3) return;
+  const double dt = st->dt;
   double v = y[i];
   for (int j = 0; j < s; ++j) {
     const double c = kA[s][j];
@@ -83,15 +85,15 @@ __global__ void k_stage(int64_t n3, int s, double dt, const double* __restrict__
   ys[i] = v;
 }
 
-__global__ void k_zero_u64(unsigned long long* p) { *p = 0ull; }
+__global__ void k_begin(RkDevState* st) { st->err_bits = 0ull; }
 
 // y5, and max_i |y5 - y4| / max(|y5|, 1e-300) (non-negative doubles order like
 // their bit patterns, so the maximum is an integer atomic max; NaN wins).
-__global__ __launch_bounds__(256) void k_finish(int64_t n3, double dt, const double* __restrict__ y,
-                                                const double* __restrict__ k, double* __restrict__ y5,
-                                                unsigned long long* err_bits) {
+__global__ __launch_bounds__(256) void k_finish(int64_t n3, RkDevState* st, const double* __restrict__ y,
+                                                const double* __restrict__ k, double* __restrict__ y5) {
   __shared__ double part[4];
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double dt = st->dt;
   double e = 0.0;
   if (i < n3) {
     double v5 = y[i], v4 = y[i];
@@ -114,15 +116,48 @@ __global__ __launch_bounds__(256) void k_finish(int64_t n3, double dt, const dou
   if (threadIdx.x == 0) {
     double m = part[0];
     for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = (part[w] != part[w] || part[w] > m) ? part[w] : m;
-    atomicMax(err_bits, (unsigned long long)__double_as_longlong(m));
+    atomicMax(&st->err_bits, (unsigned long long)__double_as_longlong(m));
   }
 }
 
+// Step control, one thread: accept if r = err / eps_RK <= 1 (finite), then
+//   accept: dt <- min(2 dt, 0.9 dt r^(-1/5))  (2 dt if r = 0)     eq. (15)
+//   reject: dt <- max(dt / 2, 0.9 dt r^(-1/4))                    eq. (14)
+// non-finite r: reject, dt / 2.  A forced decision leaves dt unchanged.
+__global__ void k_control(RkDevState* st) {
+  if (st->halted) {
+    st->ok = 0;
+    return;
+  }
+  const double err = __longlong_as_double((long long)st->err_bits);
+  const double r = err / st->eps;
+  const double dt = st->dt;
+  const bool finite = r == r && r != __longlong_as_double(0x7ff0000000000000ll);
+  const bool ok = st->force >= 0 ? st->force == 1 : (finite && r <= 1.0);
+  st->r = r;
+  st->ok = ok ? 1 : 0;
+  st->dt_used = dt;
+  if (ok) {
+    st->t = st->t + dt;
+    st->accepted += 1;
+  } else {
+    st->rejected += 1;
+  }
+  if (st->force < 0) {
+    if (!finite) st->dt = 0.5 * dt;
+    else if (ok) st->dt = r == 0.0 ? 2.0 * dt : fmin(2.0 * dt, 0.9 * dt * pow(r, -0.2));
+    else st->dt = fmax(0.5 * dt, 0.9 * dt * pow(r, -0.25));
+  }
+  if (st->accepted >= st->target) st->halted = 1;
+}
+
 // accepted step: D += dt/2 (V(y) + V(y5)) (eq. 16); y = y5
-__global__ void k_accept(int64_t n, double dt, double V0, const double* __restrict__ a, const double* __restrict__ y5,
-                         const double* __restrict__ Vstart, double* __restrict__ y, double* __restrict__ D) {
+__global__ void k_accept(int64_t n, const RkDevState* __restrict__ st, double V0, const double* __restrict__ a,
+                         const double* __restrict__ y5, const double* __restrict__ Vstart, double* __restrict__ y,
+                         double* __restrict__ D) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
+  if (i >= n || !st->ok) return;
+  const double dt = st->dt_used;
   const double phi = y5[i], tau = y5[n + i], sig = y5[2 * n + i];
   const double ai = a[i];
   const double q = tau / (ai * sig), e = phi / ai;
@@ -135,25 +170,31 @@ __global__ void k_accept(int64_t n, double dt, double V0, const double* __restri
 
 }  // namespace
 
-hipError_t launch_rk_stage(int64_t n3, int s, double dt, const double* y, const double* k, double* ys,
-                           hipStream_t st) {
+hipError_t launch_rk_stage(int64_t n3, int s, const RkDevState* st, const double* y, const double* k, double* ys,
+                           hipStream_t strm) {
   const int bs = 256;
-  hipLaunchKernelGGL(k_stage, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, st, n3, s, dt, y, k, ys);
+  hipLaunchKernelGGL(k_stage, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, strm, n3, s, st, y, k, ys);
   return hipGetLastError();
 }
 
-hipError_t launch_rk_finish(int64_t n3, double dt, const double* y, const double* k, double* y5,
-                            unsigned long long* err_bits, hipStream_t st) {
-  const int bs = 256;
-  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, st, err_bits);
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, st, n3, dt, y, k, y5, err_bits);
+hipError_t launch_rk_begin(RkDevState* st, hipStream_t strm) {
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, strm, st);
   return hipGetLastError();
 }
 
-hipError_t launch_rk_accept(int64_t n, double dt, double V0, const double* a, const double* y5, const double* Vstart,
-                            double* y, double* D, hipStream_t st) {
+hipError_t launch_rk_finish_control(int64_t n3, RkDevState* st, const double* y, const double* k, double* y5,
+                                    hipStream_t strm) {
   const int bs = 256;
-  hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, st, n, dt, V0, a, y5, Vstart, y, D);
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, strm, n3, st, y, k, y5);
+  hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, strm, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_rk_accept(int64_t n, const RkDevState* st, double V0, const double* a, const double* y5,
+                            const double* Vstart, double* y, double* D, hipStream_t strm) {
+  const int bs = 256;
+  hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, strm, n, st, V0, a, y5, Vstart, y,
+                     D);
   return hipGetLastError();
 }
 

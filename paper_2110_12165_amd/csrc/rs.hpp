@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include "device_types.hpp"
 #include "hmat.h"
 
 namespace hm {
@@ -16,15 +17,19 @@ hipError_t launch_rs_slip_rate(int64_t n, double V0, double V_pl, const double* 
 hipError_t launch_rs_rhs(int64_t n, const rs_params& p, const double* y, const double* ax, const double* bx,
                          double* dydt, hipStream_t s);
 
+// One Runge-Kutta attempt is: launch_rk_begin, six stages (launch_rk_stage
+// for stages 1..5, then slip rate, products and right-hand side), then
+// launch_rk_finish_control and launch_rk_accept.  All read the step from the
+// device state, so the sequence can be captured in a graph.
+hipError_t launch_rk_begin(RkDevState* st, hipStream_t strm);
 // Cash-Karp stage input ys = y + dt sum_{j<s} a_sj k_j (k: 6 blocks of n3).
-hipError_t launch_rk_stage(int64_t n3, int s, double dt, const double* y, const double* k, double* ys,
-                           hipStream_t st);
-// y5 and the largest relative difference |y5 - y4| / |y5| (bits of a
-// non-negative double, atomic max; cleared by the launch itself).
-hipError_t launch_rk_finish(int64_t n3, double dt, const double* y, const double* k, double* y5,
-                            unsigned long long* err_bits, hipStream_t st);
-// accepted step: slip update of eq. (16) and y = y5.
-hipError_t launch_rk_accept(int64_t n, double dt, double V0, const double* a, const double* y5, const double* Vstart,
-                            double* y, double* D, hipStream_t st);
+hipError_t launch_rk_stage(int64_t n3, int s, const RkDevState* st, const double* y, const double* k, double* ys,
+                           hipStream_t strm);
+// y5, the largest relative difference |y5 - y4| / |y5| and the step control.
+hipError_t launch_rk_finish_control(int64_t n3, RkDevState* st, const double* y, const double* k, double* y5,
+                                    hipStream_t strm);
+// accepted step (if the controller accepted): eq. (16) slip update, y = y5.
+hipError_t launch_rk_accept(int64_t n, const RkDevState* st, double V0, const double* a, const double* y5,
+                            const double* Vstart, double* y, double* D, hipStream_t strm);
 
 }  // namespace hm

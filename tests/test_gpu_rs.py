@@ -125,3 +125,42 @@ def test_plate_rate_state_stays_put(case):
     np.testing.assert_allclose(yg, y0, rtol=1e-12)
     # slip grows at the plate rate
     np.testing.assert_allclose(D.cpu().numpy(), p["V_pl"] * rk.t, rtol=1e-9)
+
+
+def test_rk45_run_graph_equals_attempts(case):
+    """rs_rk45_run (device-side control, graph replay on a side stream, and
+    direct launches) reproduces the attempt-by-attempt path bit for bit and
+    the oracle's free-running integration within tolerance."""
+    torch, hm, f, H, p, Hg, dp, dev = case
+    say("[rk45 run] planar64x32, 30 steps, graph and direct")
+    y0 = _state(f, p, 2, kick=0.02)
+    out = rk45.integrate(lambda y: fr.rhs(y, p, H.matvec), y0, 1.0, 30,
+                         slip_rate=lambda y: fr.slip_rate(y[:f.n], y[f.n:2 * f.n], y[2 * f.n:], p["a"], p["V0"]))
+    results = []
+    for mode in ("attempts", "direct", "graph"):
+        rk = hm.RK45(Hg, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+        y = torch.tensor(y0, device=dev)
+        D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+        if mode == "attempts":
+            while rk.state.accepted < 30:
+                rk.attempt(y, D)
+        elif mode == "direct":
+            rk.run(y, D, 30, use_graph=False)
+        else:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                rk.run(y, D, 10, use_graph=True, stream=s)
+                rk.run(y, D, 20, use_graph=True, stream=s)   # graph reused
+            s.synchronize()
+        results.append((y.cpu().numpy(), D.cpu().numpy(), rk.state.t, rk.state.accepted, rk.state.rejected))
+    for r in results[1:]:
+        assert np.array_equal(r[0], results[0][0]) and np.array_equal(r[1], results[0][1])
+        assert r[2] == results[0][2] and r[3] == results[0][3] == 30 and r[4] == results[0][4]
+    n = f.n
+    yg = results[0][0]
+    rej = sum(1 for e in out["log"] if not e[3])
+    assert results[0][4] == rej
+    for c in range(3):
+        sl = slice(c * n, (c + 1) * n)
+        assert np.max(np.abs(yg[sl] - out["y"][sl])) <= 1e-8 * np.max(np.abs(out["y"][sl]))
+    assert np.max(np.abs(results[0][1] - out["D"])) <= 1e-8 * np.max(np.abs(out["D"]))
