@@ -107,6 +107,8 @@ typedef struct {
   int32_t n_threads;       /* host threads for the build; 0 = all hardware threads */
   int32_t wg_waves;        /* BATCHED: waves per workgroup (4, 8 or 16); 0 = default */
   int32_t unit_kib;        /* BATCHED: target bytes per work unit in KiB; 0 = default */
+  int32_t wg_waves_p1;     /* BATCHED split: waves per workgroup of phase 1 (4, 8, 16);
+                              0 = same as wg_waves (or the default) */
 } hmat_opts;
 
 /* Fill *opts with defaults (eps 1e-6, eta 2, leaf 32, lattice 1, FP64, AUTO). */
@@ -133,6 +135,8 @@ typedef struct {
   int32_t kernel;          /* kernel actually used (AUTO resolved) */
   int32_t wg_waves;
   int32_t lattice;
+  int32_t wg_waves_p1;
+  int32_t pad;
 } hmat_stats;
 
 /* Host copy of the blocks of a handle, in cluster order (hmat_export /
@@ -215,9 +219,9 @@ hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, in
 hmat_status hmat_info(hmat_t h, hmat_stats* out);
 
 /*
- * hmat_autotune — time the BATCHED schedules (waves per workgroup, unit
- * size, split or persistent launch) on the handle's own blocks and keep the
- * fastest.  Synchronises the stream.  Products before and after give
+ * hmat_autotune — time the plain product and the BATCHED schedules (waves
+ * per workgroup of each phase, split or persistent launch) on the handle's
+ * own blocks and keep the fastest.  Synchronises the stream.  Products before and after give
  * results equal to within rounding (the summation order of a row can
  * change with the schedule).  reps: timed products per candidate (>= 1).
  */

@@ -177,8 +177,8 @@ struct hmat_s {
   }
 
   template <typename T>
-  void setup_batched(int32_t wg, int64_t unit_bytes, hipStream_t s) {
-    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes);
+  void setup_batched(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
+    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1);
     batched.units = upload(L.units, s, true);
     batched.n1 = L.n1;
     batched.n2 = L.n2;
@@ -188,19 +188,23 @@ struct hmat_s {
     batched.perm = d_perm;
     batched.ctr = alloc_zero<hm::QueueCounters>(1, s, true);
     batched.wg_waves = wg;
+    batched.wg_waves_p1 = wg1;
     grid = hm::persistent_blocks_per_cu<T>(wg) * cus;
     st.n_units_p1 = L.n1;
     st.n_units_p2 = L.n2;
     opts.wg_waves = wg;
+    opts.wg_waves_p1 = wg1;
     opts.unit_kib = (int32_t)(unit_bytes / 1024);
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
   }
 
   bool f32() const { return opts.prec == HMAT_F32; }
 
-  void setup_batched_any(int32_t wg, int64_t unit_bytes, hipStream_t s) {
-    if (f32()) setup_batched<float>(wg, unit_bytes, s);
-    else setup_batched<double>(wg, unit_bytes, s);
+  // The persistent schedule runs both phases in one launch: one wave count.
+  void setup_batched_any(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
+    if (kernel == HMAT_KERNEL_BATCHED_PERSISTENT || wg1 == 0) wg1 = wg;
+    if (f32()) setup_batched<float>(wg, unit_bytes, wg1, s);
+    else setup_batched<double>(wg, unit_bytes, wg1, s);
   }
 
   hipError_t product(bool transpose, const double* x, double* y, double alpha, double beta, hipStream_t s,
@@ -229,6 +233,8 @@ void check_opts(const hmat_opts& o, bool build) {
   if (o.kernel < HMAT_KERNEL_PLAIN || o.kernel > HMAT_KERNEL_AUTO) hm::fail(HMAT_EINVAL, "unknown kernel");
   if (o.wg_waves != 0 && o.wg_waves != 4 && o.wg_waves != 8 && o.wg_waves != 16)
     hm::fail(HMAT_EINVAL, "wg_waves must be 0, 4, 8 or 16");
+  if (o.wg_waves_p1 != 0 && o.wg_waves_p1 != 4 && o.wg_waves_p1 != 8 && o.wg_waves_p1 != 16)
+    hm::fail(HMAT_EINVAL, "wg_waves_p1 must be 0, 4, 8 or 16");
   if (o.unit_kib < 0) hm::fail(HMAT_EINVAL, "unit_kib must be >= 0");
 }
 
@@ -236,6 +242,7 @@ void check_opts(const hmat_opts& o, bool build) {
 // the planar benchmark fault; hmat_autotune can pick another).
 constexpr int32_t kAutoKernel = HMAT_KERNEL_BATCHED_SPLIT;
 constexpr int32_t kDefaultWaves = 4;
+constexpr int32_t kDefaultWavesP1 = 4;
 constexpr int32_t kDefaultUnitKiB = 256;
 
 void fill_stats(hmat_s* h);
@@ -263,8 +270,9 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
   else h->setup_plain<double>(s);
   if (h->kernel != HMAT_KERNEL_PLAIN) {
     const int32_t wg = o.wg_waves ? o.wg_waves : kDefaultWaves;
+    const int32_t wg1 = o.wg_waves_p1 ? o.wg_waves_p1 : (o.wg_waves ? o.wg_waves : kDefaultWavesP1);
     const int64_t ub = (int64_t)(o.unit_kib ? o.unit_kib : kDefaultUnitKiB) * 1024;
-    h->setup_batched_any(wg, ub, s);
+    h->setup_batched_any(wg, ub, wg1, s);
   }
   fill_stats(h.get());
   return h.release();
@@ -304,6 +312,7 @@ void refresh_stats(hmat_s* h) {
   h->st.device_bytes = h->bytes_fixed + h->bytes_batched;
   h->st.kernel = h->kernel;
   h->st.wg_waves = h->kernel == HMAT_KERNEL_PLAIN ? 0 : h->opts.wg_waves;
+  h->st.wg_waves_p1 = h->kernel == HMAT_KERNEL_PLAIN ? 0 : h->opts.wg_waves_p1;
 }
 
 void check_vectors(hmat_t h, const double* x, const double* y, int64_t nrhs, int64_t ld) {
@@ -465,25 +474,30 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
     };
     double best = time_it(HMAT_KERNEL_PLAIN);
     int32_t best_k = HMAT_KERNEL_PLAIN, best_w = 0, best_u = 0;
-    for (int32_t wg : {4, 8, 16})
-      for (int32_t ukib : {128, 512, 2048}) {
-        h->drop_batched();
-        h->setup_batched_any(wg, (int64_t)ukib * 1024, s);
-        for (int32_t k : {HMAT_KERNEL_BATCHED_SPLIT, HMAT_KERNEL_BATCHED_PERSISTENT}) {
+    int32_t best_w1 = 0;
+    const int32_t saved_kernel = h->kernel;
+    for (int32_t k : {HMAT_KERNEL_BATCHED_SPLIT, HMAT_KERNEL_BATCHED_PERSISTENT})
+      for (int32_t wg : {4, 8, 16})
+        for (int32_t wg1 : {4, 8, 16}) {
+          if (k == HMAT_KERNEL_BATCHED_PERSISTENT && wg1 != wg) continue;
+          h->drop_batched();
+          h->kernel = k;
+          h->setup_batched_any(wg, (int64_t)kDefaultUnitKiB * 1024, wg1, s);
           const double t = time_it(k);
           if (t < best) {
             best = t;
             best_k = k;
             best_w = wg;
-            best_u = ukib;
+            best_w1 = wg1;
+            best_u = kDefaultUnitKiB;
           }
         }
-      }
+    h->kernel = saved_kernel;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->drop_batched();
     h->kernel = best_k;
-    if (best_k != HMAT_KERNEL_PLAIN) h->setup_batched_any(best_w, (int64_t)best_u * 1024, s);
+    if (best_k != HMAT_KERNEL_PLAIN) h->setup_batched_any(best_w, (int64_t)best_u * 1024, best_w1, s);
     refresh_stats(h);
   });
 }

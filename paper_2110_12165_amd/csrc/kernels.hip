@@ -286,22 +286,24 @@ __global__ __launch_bounds__(64) void k_plain_p2t(PlainArgs a, const double* __r
   y[row] = beta == 0.0 ? alpha * acc : fma(alpha, acc, beta * y[row]);
 }
 
-template <typename T, int NW>
-hipError_t launch_batched_nw(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
-                             double beta, hipStream_t s, hipEvent_t* ev) {
-  if (persistent) {
-    if (ev) (void)hipEventRecord(ev[0], s);
-    if (a.n1 + a.n2 > 0)
-      hipLaunchKernelGGL((k_persistent<T, NW>), dim3(grid), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
-    if (ev) (void)hipEventRecord(ev[1], s);
-    return hipGetLastError();
+template <typename T, int PHASE>
+void launch_phase(const BatchedArgs& a, int nw, unsigned grid, const double* x, double* y, double alpha, double beta,
+                  hipStream_t s) {
+  switch (nw) {
+    case 4: hipLaunchKernelGGL((k_phase<T, 4, PHASE>), dim3(grid), dim3(4 * 64), 0, s, a, x, y, alpha, beta); break;
+    case 8: hipLaunchKernelGGL((k_phase<T, 8, PHASE>), dim3(grid), dim3(8 * 64), 0, s, a, x, y, alpha, beta); break;
+    default: hipLaunchKernelGGL((k_phase<T, 16, PHASE>), dim3(grid), dim3(16 * 64), 0, s, a, x, y, alpha, beta);
   }
-  if (ev) (void)hipEventRecord(ev[0], s);
-  if (a.n1 > 0) hipLaunchKernelGGL((k_phase<T, NW, 1>), dim3(a.n1), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
-  if (ev) (void)hipEventRecord(ev[1], s);
-  if (a.n2 > 0) hipLaunchKernelGGL((k_phase<T, NW, 2>), dim3(a.n2), dim3(NW * 64), 0, s, a, x, y, alpha, beta);
-  if (ev) (void)hipEventRecord(ev[2], s);
-  return hipGetLastError();
+}
+
+template <typename T>
+void launch_persistent(const BatchedArgs& a, int nw, int grid, const double* x, double* y, double alpha, double beta,
+                       hipStream_t s) {
+  switch (nw) {
+    case 4: hipLaunchKernelGGL((k_persistent<T, 4>), dim3(grid), dim3(4 * 64), 0, s, a, x, y, alpha, beta); break;
+    case 8: hipLaunchKernelGGL((k_persistent<T, 8>), dim3(grid), dim3(8 * 64), 0, s, a, x, y, alpha, beta); break;
+    default: hipLaunchKernelGGL((k_persistent<T, 16>), dim3(grid), dim3(16 * 64), 0, s, a, x, y, alpha, beta);
+  }
 }
 
 template <typename T, int NW>
@@ -316,12 +318,21 @@ int occupancy_nw() {
 template <typename T>
 hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
                           double beta, hipStream_t s, hipEvent_t* ev) {
-  switch (a.wg_waves) {
-    case 4: return launch_batched_nw<T, 4>(a, persistent, grid, x, y, alpha, beta, s, ev);
-    case 8: return launch_batched_nw<T, 8>(a, persistent, grid, x, y, alpha, beta, s, ev);
-    case 16: return launch_batched_nw<T, 16>(a, persistent, grid, x, y, alpha, beta, s, ev);
-    default: return hipErrorInvalidValue;
+  const auto ok = [](int w) { return w == 4 || w == 8 || w == 16; };
+  if (!ok(a.wg_waves) || !ok(a.wg_waves_p1)) return hipErrorInvalidValue;
+  if (persistent) {
+    if (a.wg_waves_p1 != a.wg_waves) return hipErrorInvalidValue;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    if (a.n1 + a.n2 > 0) launch_persistent<T>(a, a.wg_waves, grid, x, y, alpha, beta, s);
+    if (ev) (void)hipEventRecord(ev[1], s);
+    return hipGetLastError();
   }
+  if (ev) (void)hipEventRecord(ev[0], s);
+  if (a.n1 > 0) launch_phase<T, 1>(a, a.wg_waves_p1, (unsigned)a.n1, x, y, alpha, beta, s);
+  if (ev) (void)hipEventRecord(ev[1], s);
+  if (a.n2 > 0) launch_phase<T, 2>(a, a.wg_waves, (unsigned)a.n2, x, y, alpha, beta, s);
+  if (ev) (void)hipEventRecord(ev[2], s);
+  return hipGetLastError();
 }
 
 template <typename T>

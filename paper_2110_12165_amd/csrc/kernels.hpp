@@ -32,7 +32,8 @@ struct BatchedArgs {
   const void* pool;
   const int32_t* perm;
   QueueCounters* ctr;
-  int32_t wg_waves;
+  int32_t wg_waves;     // waves per workgroup, phase-2 units (and the persistent launch)
+  int32_t wg_waves_p1;  // waves per workgroup, phase-1 units
 };
 
 // ev (optional): events recorded before the first launch, between the

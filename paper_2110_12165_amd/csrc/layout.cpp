@@ -131,10 +131,11 @@ PlainLayout<T> make_plain(const HostMatrix& H, bool transpose) {
 }
 
 template <typename T>
-BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes) {
+BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1) {
   constexpr int W = 16 / (int)sizeof(T);
   BatchedLayout<T> L;
   L.wg_waves = wg_waves;
+  L.wg_waves_p1 = wg_waves_p1;
   L.unit_bytes = unit_bytes;
   const int64_t nb = H.nblocks();
 
@@ -168,9 +169,9 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
   int64_t t = 1;                                // t[0] is the zero pad
   for (auto& g : groups) {
     const int64_t nq = (g.n + W - 1) / W;
-    g.RG = (int)std::max<int64_t>(1, std::min<int64_t>(wg_waves, nq / kMinQuads));
+    g.RG = (int)std::max<int64_t>(1, std::min<int64_t>(wg_waves_p1, nq / kMinQuads));
     const int64_t need = (g.R + 63) / 64;
-    g.S = (int)std::max<int64_t>(1, std::min<int64_t>(need, wg_waves / g.RG));
+    g.S = (int)std::max<int64_t>(1, std::min<int64_t>(need, wg_waves_p1 / g.RG));
     while (g.S > 1 && 64LL * g.S * g.n * (int64_t)sizeof(T) > unit_bytes) --g.S;
     g.base = t;
     for (int32_t b : g.blocks) {
@@ -199,8 +200,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
       u.in0 = to_i32(g.c0, "row");
       u.nin = (int32_t)g.n;
       u.out0 = to_i32(g.base + s0, "intermediate index");
-      u.off = off = align_elems<T>(off);
-      off += (int64_t)u.nq * W * ns;
+      u.off = 0;
       pend.push_back({u, 1, gi, s0});
     }
   }
@@ -234,11 +234,22 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     }
     u.nq = to_i32(K / W, "unit inputs");
     u.nin = (int32_t)K;
-    u.off = off = align_elems<T>(off);
-    off += K * m;
+    u.off = 0;
     pend.push_back({u, 2, k, 0});
   }
   to_i32((int64_t)L.src.size(), "input list");
+  // Dispatch order: phase 1 before phase 2, larger units first.  Panels are
+  // laid out in that same order, so workgroups running at the same time
+  // stream neighbouring regions of the pool.
+  auto bytes = [](const Unit& u) { return (int64_t)u.nq * u.nout; };
+  std::stable_sort(pend.begin(), pend.end(), [&](const Pending& a, const Pending& b) {
+    if (a.kind != b.kind) return a.kind < b.kind;
+    return bytes(a.u) > bytes(b.u);
+  });
+  for (auto& p : pend) {
+    p.u.off = off = align_elems<T>(off);
+    off += (int64_t)p.u.nq * W * p.u.nout;
+  }
   L.pool.assign(align_elems<T>(off) + 256 / sizeof(T), T(0));
 
   // ---- fill panels ----------------------------------------------------------
@@ -290,9 +301,6 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     }
     (p.kind == 1 ? p1 : p2).push_back(u);
   }
-  auto bytes = [](const Unit& u) { return (int64_t)u.nq * u.nout; };
-  std::stable_sort(p1.begin(), p1.end(), [&](const Unit& a, const Unit& b) { return bytes(a) > bytes(b); });
-  std::stable_sort(p2.begin(), p2.end(), [&](const Unit& a, const Unit& b) { return bytes(a) > bytes(b); });
   L.n1 = (int32_t)p1.size();
   L.n2 = (int32_t)p2.size();
   L.units = std::move(p1);
@@ -302,7 +310,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
 
 template PlainLayout<float> make_plain<float>(const HostMatrix&, bool);
 template PlainLayout<double> make_plain<double>(const HostMatrix&, bool);
-template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t);
-template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t);
+template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t, int32_t);
+template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t, int32_t);
 
 }  // namespace hm

@@ -34,12 +34,15 @@ struct BatchedLayout {
   int32_t n1 = 0, n2 = 0;
   std::vector<int32_t> src;
   int64_t t_size = 0;                  // intermediate values, entry 0 = zero pad
-  int32_t wg_waves = 8;
+  int32_t wg_waves = 8;                // waves per workgroup of phase-2 units
+  int32_t wg_waves_p1 = 8;             // waves per workgroup of phase-1 units
   int64_t unit_bytes = 0;
 };
 
+// wg_waves: waves per workgroup of phase-2 units; wg_waves_p1: of phase-1
+// units (equal for the persistent schedule, which runs both in one launch).
 template <typename T>
-BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes);
+BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1);
 
 // Row intervals of the finest common refinement of the blocks' row (or
 // column) ranges, each split into pieces of at most `cap` rows.

@@ -25,11 +25,11 @@ static void die(const char* m, long a = 0, long b = 0) {
 }
 
 template <typename T>
-static double replay(const HostMatrix& H, int NW, int64_t unit_bytes, const std::vector<double>& x,
+static double replay(const HostMatrix& H, int NW, int NW1, int64_t unit_bytes, const std::vector<double>& x,
                      const std::vector<double>& yref) {
   constexpr int W = 16 / (int)sizeof(T);
   constexpr int kStage = 2048;
-  BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes);
+  BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes, NW1);
   const int64_t n = H.n;
   std::vector<double> t(L.t_size, 0.0), y(n, 0.0);
   std::vector<unsigned char> touched(L.pool.size(), 0);
@@ -40,11 +40,12 @@ static double replay(const HostMatrix& H, int NW, int64_t unit_bytes, const std:
       const Unit& u = L.units[ui];
       if (u.kind != pass) continue;
       if (ui < L.n1 && u.kind != 1) die("phase-2 unit among phase-1 units", ui);
-      if (u.S < 1 || u.RG < 1 || u.S * u.RG > NW) die("bad S/RG", u.S, u.RG);
+      const int NWu = u.kind == 1 ? NW1 : NW;
+      if (u.S < 1 || u.RG < 1 || u.S * u.RG > NWu) die("bad S/RG", u.S, u.RG);
       if (u.nout < 1 || u.nout > 64 * u.S) die("bad nout", u.nout, u.S);
       const int nin_pad = u.nq * W;
-      std::vector<double> zs(kStage), red((size_t)NW * 64, 0.0);
-      std::vector<double> acc((size_t)NW * 64, 0.0);
+      std::vector<double> zs(kStage), red((size_t)NWu * 64, 0.0);
+      std::vector<double> acc((size_t)NWu * 64, 0.0);
       for (int c0 = 0; c0 < nin_pad; c0 += kStage) {
         const int cl = std::min(kStage, nin_pad - c0);
         if (cl % W) die("stage not a multiple of W", cl);
@@ -70,7 +71,7 @@ static double replay(const HostMatrix& H, int NW, int64_t unit_bytes, const std:
           }
           zs[i] = v;
         }
-        for (int wave = 0; wave < NW; ++wave) {
+        for (int wave = 0; wave < NWu; ++wave) {
           const bool working = wave < u.S * u.RG;
           const int sg = wave % u.S, rg = wave / u.S;
           for (int lane = 0; lane < 64; ++lane) {
@@ -90,7 +91,7 @@ static double replay(const HostMatrix& H, int NW, int64_t unit_bytes, const std:
           }
         }
       }
-      for (int wave = 0; wave < NW; ++wave) {
+      for (int wave = 0; wave < NWu; ++wave) {
         const int sg = wave % u.S, rg = wave / u.S;
         if (rg != 0) continue;
         for (int lane = 0; lane < 64; ++lane) {
@@ -99,7 +100,7 @@ static double replay(const HostMatrix& H, int NW, int64_t unit_bytes, const std:
           double sum = 0.0;
           for (int r = 0; r < u.RG; ++r) {
             const int idx = (r * u.S + sg) * 64 + lane;
-            if (idx >= NW * 64) die("reduction index", idx);
+            if (idx >= NWu * 64) die("reduction index", idx);
             sum += acc[idx];
           }
           if (u.kind == 1) {
@@ -177,10 +178,11 @@ int main(int argc, char** argv) {
   }
   for (int64_t i = 0; i < n; ++i) yref[H.perm[i]] = yc[i];
   for (int NW : {4, 8, 16})
-    for (int64_t ub : {64 << 10, 256 << 10, 4 << 20}) {
-      const double r64 = replay<double>(H, NW, ub, x, yref);
-      const double r32 = replay<float>(H, NW, ub, x, yref);
-      std::printf("NW=%d unit=%ld rel64=%.3e rel32=%.3e\n", NW, (long)ub, r64, r32);
+    for (int NW1 : {4, 8, 16})
+    for (int64_t ub : {64 << 10, 4 << 20}) {
+      const double r64 = replay<double>(H, NW, NW1, ub, x, yref);
+      const double r32 = replay<float>(H, NW, NW1, ub, x, yref);
+      std::printf("NW=%d NW1=%d unit=%ld rel64=%.3e rel32=%.3e\n", NW, NW1, (long)ub, r64, r32);
       if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed product differs");
     }
   std::printf("OK\n");
