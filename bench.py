@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 
 # Dominant kernel of each schedule (launch index -> kernel symbol of the FP32 build).
 DOMINANT_SYMBOL = {
-    ("split", 1): "k_phase<float, 4, 2> (phase 2: y = D x + U t)",
+    ("split", 1): "k_phase<float, 8, 2> (phase 2: y = D x + U t)",
     ("split", 0): "k_phase<float, 4, 1> (phase 1: t = V^T x)",
     ("persistent", 0): "k_persistent<float, 4>",
     ("plain", 1): "k_plain_p2<float>",
@@ -267,7 +267,7 @@ def main():
             "aca_eps": w["aca_eps"], "leaf": w["leaf"], "eta": w["eta"], "lattice": w["lattice"],
             "x": "log-uniform [1e-12, 1e-9] m/s, seed 2",
             "factor_storage": "f32", "accumulate": "f64", "kernel": info["kernel"],
-            "wg_waves": info["wg_waves"],
+            "wg_waves": info["wg_waves"], "wg_waves_p1": info["wg_waves_p1"],
             "parallelism": "single GPU",
         },
         "roofline": {

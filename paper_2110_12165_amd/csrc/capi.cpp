@@ -241,7 +241,7 @@ void check_opts(const hmat_opts& o, bool build) {
 // Default schedule of the batched product (fastest measured on MI355X for
 // the planar benchmark fault; hmat_autotune can pick another).
 constexpr int32_t kAutoKernel = HMAT_KERNEL_BATCHED_SPLIT;
-constexpr int32_t kDefaultWaves = 4;
+constexpr int32_t kDefaultWaves = 8;
 constexpr int32_t kDefaultWavesP1 = 4;
 constexpr int32_t kDefaultUnitKiB = 256;
 
@@ -270,7 +270,7 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
   else h->setup_plain<double>(s);
   if (h->kernel != HMAT_KERNEL_PLAIN) {
     const int32_t wg = o.wg_waves ? o.wg_waves : kDefaultWaves;
-    const int32_t wg1 = o.wg_waves_p1 ? o.wg_waves_p1 : (o.wg_waves ? o.wg_waves : kDefaultWavesP1);
+    const int32_t wg1 = o.wg_waves_p1 ? o.wg_waves_p1 : kDefaultWavesP1;
     const int64_t ub = (int64_t)(o.unit_kib ? o.unit_kib : kDefaultUnitKiB) * 1024;
     h->setup_batched_any(wg, ub, wg1, s);
   }

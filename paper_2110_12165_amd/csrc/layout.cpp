@@ -168,22 +168,14 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
   std::vector<int64_t> slot_of_block(nb, -1);  // t index of (block, column 0)
   int64_t t = 1;                                // t[0] is the zero pad
   for (auto& g : groups) {
-    // (S, RG) with S * RG <= waves: most busy waves first, then more outputs
-    // per unit (fewer, larger units), within the unit-size cap.
+    // Row groups first (at least kMinQuads input groups per wave), then as
+    // many output groups as the remaining waves allow.  Measured on the
+    // benchmark fault: more, shorter per-wave loops beat fewer, fuller units.
     const int64_t nq = (g.n + W - 1) / W;
-    const int64_t rg_max = std::max<int64_t>(1, std::min<int64_t>(wg_waves_p1, nq / kMinQuads));
+    g.RG = (int)std::max<int64_t>(1, std::min<int64_t>(wg_waves_p1, nq / kMinQuads));
     const int64_t need = (g.R + 63) / 64;
-    int64_t best_busy = -1;
-    for (int64_t S = 1; S <= wg_waves_p1; ++S) {
-      if (S > 1 && (S > need || 64LL * S * g.n * (int64_t)sizeof(T) > unit_bytes)) break;
-      const int64_t RG = std::min<int64_t>(rg_max, wg_waves_p1 / S);
-      const int64_t busy = std::min<int64_t>(S, need) * RG;
-      if (busy >= best_busy) {
-        best_busy = busy;
-        g.S = (int)S;
-        g.RG = (int)RG;
-      }
-    }
+    g.S = (int)std::max<int64_t>(1, std::min<int64_t>(need, wg_waves_p1 / g.RG));
+    while (g.S > 1 && 64LL * g.S * g.n * (int64_t)sizeof(T) > unit_bytes) --g.S;
     g.base = t;
     for (int32_t b : g.blocks) {
       slot_of_block[b] = t;

@@ -15,20 +15,20 @@ from __future__ import annotations
 
 from synth import WORKLOADS
 
-# workload -> (wg_waves, unit_kib, kernel) chosen by hmat_autotune on MI355X
+# workload -> (wg_waves phase 2, wg_waves phase 1, kernel): fastest measured on MI355X
 TUNED = {
-    "dip30_480x256": (4, 256, "split"),
+    "dip30_480x256": (8, 4, "split"),
 }
 
 
 def bench_options(workload: str, variant: str) -> dict:
     w = WORKLOADS[workload]
     base = dict(aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"])
-    wg, ukib, kern = TUNED.get(workload, (4, 256, "split"))
+    wg, wg1, kern = TUNED.get(workload, (8, 4, "split"))
     if variant == "batched_f32":
-        return dict(base, prec="f32", kernel=kern, wg_waves=wg, unit_kib=ukib)
+        return dict(base, prec="f32", kernel=kern, wg_waves=wg, wg_waves_p1=wg1)
     if variant == "batched_f64":
-        return dict(base, prec="f64", kernel=kern, wg_waves=wg, unit_kib=ukib)
+        return dict(base, prec="f64", kernel=kern, wg_waves=wg, wg_waves_p1=wg1)
     if variant == "plain_f64":
         return dict(base, prec="f64", kernel="plain")
     raise ValueError(f"unknown variant {variant}")
