@@ -108,8 +108,18 @@ typedef struct {
   int32_t wg_waves;        /* BATCHED: waves per workgroup (4, 8 or 16); 0 = default */
   int32_t unit_kib;        /* BATCHED: target bytes per work unit in KiB; 0 = default */
   int32_t wg_waves_p1;     /* BATCHED split: waves per workgroup of phase 1 (4, 8, 16);
-                              0 = same as wg_waves (or the default) */
+                              0 = default (4) */
+  int32_t max_nrhs;        /* > 0: allocate the buffers of hmat_matmat at creation (needs
+                              HMAT_F32, a BATCHED kernel and wg_waves_p1 <= 4); 0: none */
 } hmat_opts;
+
+/* Arithmetic of hmat_matmat: FP32 factors and member values are split into
+ * bf16 parts (each the bf16 rounding of the remaining error) and the cross
+ * products with part indices i + j < parts are accumulated in FP32 on MFMA. */
+typedef enum {
+  HMAT_MM_BF16X3 = 2,      /* 2 parts, 3 products: about 16 significant bits */
+  HMAT_MM_BF16X6 = 3       /* 3 parts (exact FP32), 6 products: FP32-level accuracy */
+} hmat_mm_mode;
 
 /* Fill *opts with defaults (eps 1e-6, eta 2, leaf 32, lattice 1, FP64, AUTO). */
 void hmat_default_opts(hmat_opts* opts);
@@ -212,6 +222,21 @@ hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int6
                         double alpha, double beta, void* stream);
 
 /* hmat_matvec_T — y = alpha * H^T x + beta * y; same arguments and rules. */
+
+/*
+ * hmat_matmat — Y = alpha * H X + beta * Y for nrhs members at once
+ * (ensemble of simulations; eq. (20) applied to a block of vectors): the
+ * products of every work unit run on MFMA (v_mfma_f32_16x16x32_bf16) with the
+ * split arithmetic of `mode` (hmat_mm_mode).
+ *   X, Y: DEVICE FP64, caller's element order, element-major:
+ *     X[i * ldx + r], Y[i * ldy + r] for element i < n, member r < nrhs;
+ *     ldx, ldy >= nrhs; X and Y must not overlap.  Members are processed in
+ *     groups of 64.
+ *   Requires a handle created with max_nrhs > 0 (HMAT_ESTATE otherwise).
+ *   Allocates nothing and does not wait for the GPU.
+ */
+hmat_status hmat_matmat(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrhs, double alpha,
+                        double beta, int32_t mode, void* stream);
 hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld,
                           double alpha, double beta, void* stream);
 

@@ -50,7 +50,7 @@ class HMatrix:
     # -- construction -------------------------------------------------------
     @staticmethod
     def _opts(aca_eps=1e-6, eta=2.0, leaf=32, lattice=1, max_rank=0, prec="f64", kernel="auto",
-              n_threads=0, wg_waves=0, unit_kib=0, wg_waves_p1=0):
+              n_threads=0, wg_waves=0, unit_kib=0, wg_waves_p1=0, max_nrhs=0):
         lib = _lib.load()
         o = _lib.HmatOpts()
         lib.hmat_default_opts(C.byref(o))
@@ -58,6 +58,7 @@ class HMatrix:
         o.prec = _lib.PREC[prec]
         o.kernel = _lib.KERNEL[kernel]
         o.n_threads, o.wg_waves, o.unit_kib, o.wg_waves_p1 = n_threads, wg_waves, unit_kib, wg_waves_p1
+        o.max_nrhs = max_nrhs
         return o
 
     @classmethod
@@ -128,6 +129,23 @@ class HMatrix:
 
     def matvec_T(self, x, y=None, alpha=1.0, beta=0.0, stream=None):
         return self._apply(self._lib.hmat_matvec_T, x, y, alpha, beta, stream)
+
+    def matmat(self, X, Y=None, alpha=1.0, beta=0.0, mode="x6", stream=None):
+        """Y = alpha H X + beta Y on MFMA (hmat_matmat).  X: float64 GPU tensor
+        (n, k), row-major (element-major: the k members of an element are
+        contiguous)."""
+        torch = _torch()
+        n = self.n
+        if not (X.is_cuda and X.dtype == torch.float64 and X.dim() == 2 and X.shape[0] == n):
+            raise ValueError("X must be a float64 GPU tensor of shape (n, k)")
+        Xc = X.contiguous()
+        out = torch.empty_like(Xc) if Y is None else Y
+        if out.shape != Xc.shape or not out.is_contiguous() or out.dtype != torch.float64:
+            raise ValueError("Y must be a contiguous float64 tensor shaped like X")
+        k = Xc.shape[1]
+        check(self._lib.hmat_matmat(self._h, _dptr(Xc), k, _dptr(out), k, k, alpha, 0.0 if Y is None else beta,
+                                    _lib.MM_MODE[mode], _stream_ptr(stream)))
+        return out
 
     def matvec_raw(self, x_ptr, y_ptr, nrhs=1, ld=None, alpha=1.0, beta=0.0, stream_ptr=None, transpose=False):
         """Direct call with device addresses (no tensor checks)."""

@@ -13,6 +13,7 @@ STATUS = {0: "HMAT_OK", -1: "HMAT_EINVAL", -2: "HMAT_ENOMEM", -3: "HMAT_EDEVICE"
 PREC = {"f64": 0, "f32": 1}
 KERNEL = {"plain": 0, "split": 1, "persistent": 2, "auto": 3}
 KERNEL_NAME = {v: k for k, v in KERNEL.items()}
+MM_MODE = {"x3": 2, "x6": 3}
 GF_FS_RECT_COPLANAR = 1
 
 
@@ -28,7 +29,8 @@ class HmatGreen(C.Structure):
 class HmatOpts(C.Structure):
     _fields_ = [("aca_eps", C.c_double), ("eta", C.c_double), ("leaf", C.c_int32), ("lattice", C.c_int32),
                 ("max_rank", C.c_int32), ("prec", C.c_int32), ("kernel", C.c_int32), ("n_threads", C.c_int32),
-                ("wg_waves", C.c_int32), ("unit_kib", C.c_int32), ("wg_waves_p1", C.c_int32)]
+                ("wg_waves", C.c_int32), ("unit_kib", C.c_int32), ("wg_waves_p1", C.c_int32),
+                ("max_nrhs", C.c_int32)]
 
 
 class HmatStats(C.Structure):
@@ -73,6 +75,8 @@ SIGNATURES = {
                               C.c_void_p]),
     "hmat_matvec_T": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_double, C.c_double,
                                 C.c_void_p]),
+    "hmat_matmat": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int64, C.c_int64, C.c_double,
+                              C.c_double, C.c_int32, C.c_void_p]),
     "hmat_info": (C.c_int, [C.c_void_p, C.POINTER(HmatStats)]),
     "hmat_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p]),
     "hmat_profile": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.POINTER(HmatProfile)]),

@@ -13,6 +13,7 @@
 #include "hmat.h"
 #include "hmat_internal.hpp"
 #include "kernels.hpp"
+#include "kernels_mm.hpp"
 #include "layout.hpp"
 #include "rs.hpp"
 
@@ -74,6 +75,11 @@ struct hmat_s {
   hm::BatchedArgs batched{};
   int grid = 0;
   int cus = 0;
+  int32_t* d_invperm = nullptr;  // ensemble product: user element -> cluster position
+  void* mm_xs = nullptr;         // ensemble product: bf16 [3][64][n]
+  void* mm_ts = nullptr;         // ensemble product: bf16 [3][64][t_size]
+  int64_t t_size = 0;
+  int32_t max_nout_p1 = 0;
   double* rs_x = nullptr;  // n doubles: slip rate minus plate rate (rs_rhs scratch)
   double* rs_ax = nullptr;  // n doubles: A (V - V_pl)
   double* rs_bx = nullptr;  // n doubles: B (V - V_pl)
@@ -189,6 +195,14 @@ struct hmat_s {
     batched.ctr = alloc_zero<hm::QueueCounters>(1, s, true);
     batched.wg_waves = wg;
     batched.wg_waves_p1 = wg1;
+    t_size = L.t_size;
+    max_nout_p1 = 0;
+    for (int32_t i = 0; i < L.n1; ++i) max_nout_p1 = std::max(max_nout_p1, L.units[i].nout);
+    if (opts.max_nrhs > 0) {
+      if (opts.prec != HMAT_F32) hm::fail(HMAT_EUNSUPPORTED, "the ensemble product needs FP32 storage");
+      if (max_nout_p1 > 256) hm::fail(HMAT_EUNSUPPORTED, "the ensemble product needs wg_waves_p1 <= 4");
+      mm_ts = alloc_zero<uint16_t>((size_t)3 * 64 * L.t_size, s, true);
+    }
     grid = hm::persistent_blocks_per_cu<T>(wg) * cus;
     st.n_units_p1 = L.n1;
     st.n_units_p2 = L.n2;
@@ -236,6 +250,7 @@ void check_opts(const hmat_opts& o, bool build) {
   if (o.wg_waves_p1 != 0 && o.wg_waves_p1 != 4 && o.wg_waves_p1 != 8 && o.wg_waves_p1 != 16)
     hm::fail(HMAT_EINVAL, "wg_waves_p1 must be 0, 4, 8 or 16");
   if (o.unit_kib < 0) hm::fail(HMAT_EINVAL, "unit_kib must be >= 0");
+  if (o.max_nrhs < 0) hm::fail(HMAT_EINVAL, "max_nrhs must be >= 0");
 }
 
 // Default schedule of the batched product (fastest measured on MI355X for
@@ -263,6 +278,13 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
   h->cus = std::max(1, cus);
   const int64_t n = h->H.n;
   h->d_perm = h->upload(h->H.perm, s);
+  if (o.max_nrhs > 0) {
+    if (h->kernel == HMAT_KERNEL_PLAIN) hm::fail(HMAT_EUNSUPPORTED, "the ensemble product needs a BATCHED kernel");
+    std::vector<int32_t> inv(n);
+    for (int64_t k = 0; k < n; ++k) inv[h->H.perm[k]] = (int32_t)k;
+    h->d_invperm = h->upload(inv, s);
+    h->mm_xs = h->alloc_zero<uint16_t>((size_t)3 * 64 * n, s);
+  }
   h->rs_x = h->alloc_zero<double>((size_t)n, s);
   h->rs_ax = h->alloc_zero<double>((size_t)n, s);
   h->rs_bx = h->alloc_zero<double>((size_t)n, s);
@@ -433,6 +455,47 @@ hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, in
     const hipStream_t s = static_cast<hipStream_t>(stream);
     for (int64_t c = 0; c < nrhs; ++c)
       check_hip(h->product(true, x + c * ld, y + c * ld, alpha, beta, s, HMAT_KERNEL_PLAIN), "transpose launch");
+  });
+}
+
+hmat_status hmat_matmat(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrhs, double alpha,
+                        double beta, int32_t mode, void* stream) {
+  return guarded([&] {
+    if (!h) hm::fail(HMAT_EINVAL, "null handle");
+    if (!h->on_device) hm::fail(HMAT_ESTATE, "handle holds host blocks only (hmat_build_host)");
+    if (nrhs < 0) hm::fail(HMAT_EINVAL, "nrhs must be >= 0");
+    if (nrhs == 0) return;
+    if (!h->mm_xs || !h->mm_ts) hm::fail(HMAT_ESTATE, "handle created without max_nrhs");
+    if (mode != HMAT_MM_BF16X3 && mode != HMAT_MM_BF16X6) hm::fail(HMAT_EINVAL, "unknown mode");
+    if (!X || !Y) hm::fail(HMAT_EINVAL, "X and Y must be non-null");
+    if (ldx < nrhs || ldy < nrhs) hm::fail(HMAT_EINVAL, "ldx and ldy must be >= nrhs");
+    const int64_t n = h->H.n;
+    const char* xa = reinterpret_cast<const char*>(X);
+    const char* ya = reinterpret_cast<const char*>(Y);
+    const int64_t sx = ((n - 1) * ldx + nrhs) * 8, sy = ((n - 1) * ldy + nrhs) * 8;
+    if (xa < ya + sy && ya < xa + sx) hm::fail(HMAT_EINVAL, "X and Y must not overlap");
+    DeviceGuard g(h->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
+      hm::MMArgs a{};
+      a.units = h->batched.units;
+      a.n1 = h->batched.n1;
+      a.n2 = h->batched.n2;
+      a.src = h->batched.src;
+      a.pool = h->batched.pool;
+      a.perm = h->d_perm;
+      a.invperm = h->d_invperm;
+      a.n = n;
+      a.t_size = h->t_size;
+      a.Xs = h->mm_xs;
+      a.Ts = h->mm_ts;
+      a.X = X + c0;
+      a.ldx = ldx;
+      a.Y = Y + c0;
+      a.ldy = ldy;
+      a.nrhs = (int32_t)std::min<int64_t>(64, nrhs - c0);
+      check_hip(hm::launch_mm(a, mode, alpha, beta, s), "ensemble launch");
+    }
   });
 }
 

@@ -103,6 +103,10 @@ WORKLOADS = {
                          aca_eps=1e-6, leaf=32, eta=2.0, lattice=8, seed=12),
     "strike_37x23": dict(mesh=(37, 23, 100.0, 90.0, "strike"),
                          aca_eps=1e-5, leaf=20, eta=2.0, lattice=2, seed=13),
+    # ensemble workload: N = 21000 (size of the paper-scale nonplanar mesh
+    # used for many-member runs), planar stand-in, 64 members
+    "dip30_150x140": dict(mesh=(150, 140, 100.0, 30.0, "dip"),
+                          aca_eps=1e-6, leaf=32, eta=2.0, lattice=8, seed=3),
 }
 
 

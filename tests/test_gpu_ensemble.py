@@ -1,0 +1,74 @@
+"""GPU parity of the ensemble product Y = H X on MFMA (eq. 20 for a block
+of members) against the FP64 oracle, on shared factors.
+
+Tolerances from the arithmetic: FP32 storage (unit roundoff 6e-8) and FP32
+accumulation on MFMA over up to a few thousand inputs per row:
+* BF16x6 (three bf16 parts represent each FP32 operand exactly; the dropped
+  cross products are O(2^-24)): relative error <= 2e-5, as the FP32 path;
+* BF16x3 (two parts, 16 significant bits; dropped terms O(2^-16) per
+  product, about 4.6e-5 relative, amplified by cancellation in the row
+  sums): relative error <= 1e-3.
+"""
+import numpy as np
+import pytest
+
+from _util import oracle_blocks, rel, say
+from oracle.greens import CoplanarRectGeometry
+from oracle.hmatrix import HMatrix as OracleH
+from synth import WORKLOADS, config_fault, loguniform_rates
+from synth.faults import MU, NU
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", params=["dip30_150x70", "planar64x32"])
+def case(request):
+    import torch
+
+    import paper_2110_12165_amd as hm
+    name = request.param
+    w = WORKLOADS[name]
+    f = config_fault(name)
+    g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
+    H = OracleH.build(g, w["leaf"], w["eta"], w["aca_eps"], w["lattice"])
+    B = oracle_blocks(H)
+    Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec="f32", kernel="split",
+                                wg_waves=8, wg_waves_p1=4, max_nrhs=64)
+    return torch, hm, name, f, H, Hg
+
+
+@pytest.mark.parametrize("mode,tol", [("x6", 2e-5), ("x3", 1e-3)])
+def test_ensemble_parity(case, mode, tol):
+    torch, hm, name, f, H, Hg = case
+    dev = torch.device("cuda:0")
+    X = loguniform_rates(f.n, 3, nrhs=64)
+    ref = H.matvec(X)
+    Y = Hg.matmat(torch.tensor(X, device=dev), mode=mode).cpu().numpy()
+    r = rel(Y, ref)
+    say(f"[ensemble] {name} N={f.n} {mode}: rel {r:.3e}")
+    assert r <= tol
+    # every member separately within the same bound
+    per = np.linalg.norm(Y - ref, axis=0) / np.linalg.norm(ref, axis=0)
+    assert per.max() <= 2 * tol
+
+
+def test_ensemble_partial_groups_alpha_beta(case):
+    torch, hm, name, f, H, Hg = case
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(8)
+    for k in (1, 5, 70):
+        X = rng.standard_normal((f.n, k))
+        Y0 = rng.standard_normal((f.n, k))
+        Y = torch.tensor(Y0, device=dev)
+        Hg.matmat(torch.tensor(X, device=dev), Y=Y, alpha=-0.5, beta=2.0, mode="x6")
+        ref = -0.5 * H.matvec(X) + 2.0 * Y0
+        assert rel(Y.cpu().numpy(), ref) <= 2e-5, k
+
+
+def test_ensemble_matches_single_vector_products(case):
+    torch, hm, name, f, H, Hg = case
+    dev = torch.device("cuda:0")
+    X = torch.tensor(loguniform_rates(f.n, 4, nrhs=16), device=dev)
+    Ym = Hg.matmat(X, mode="x6").cpu().numpy()
+    Yv = np.stack([Hg.matvec(X[:, c].contiguous()).cpu().numpy() for c in range(16)], axis=1)
+    assert rel(Ym, Yv) <= 2e-5
