@@ -177,6 +177,65 @@ def rk45_run(torch, hm, f, w, x_np, n_steps):
                     "d_c=0.01 m, sigma=50 MPa, V_pl=1e-9 m/s; start from steady state at the benchmark slip rates"}
 
 
+def ensemble(torch, hm, workloads, reps=20):
+    """64-member ensemble product on MFMA (hmat_matmat, BF16x6 and BF16x3)
+    against 64 single-vector FP32 batched products on the same handle."""
+    from paper_2110_12165_amd.tuning import bench_options
+    from synth import WORKLOADS, config_fault, loguniform_rates
+    from synth.faults import MU, NU
+
+    out = {}
+    dev = torch.device("cuda:0")
+    for name in workloads:
+        w = WORKLOADS[name]
+        f = config_fault(name)
+        opts = bench_options(name, "batched_f32") if name in ("dip30_480x256",) else dict(
+            aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"], prec="f32",
+            kernel="split", wg_waves=8, wg_waves_p1=4)
+        H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, max_nrhs=64, **opts)
+        info = H.info()
+        X = torch.tensor(loguniform_rates(f.n, 3, nrhs=64), device=dev)
+        Y = torch.empty_like(X)
+        cols = [X[:, c].contiguous() for c in range(64)]
+        yv = torch.empty(f.n, dtype=torch.float64, device=dev)
+
+        def timed(fn):
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fn()
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / reps
+
+        ms_x6 = timed(lambda: H.matmat(X, Y=Y, mode="x6"))
+        ms_x3 = timed(lambda: H.matmat(X, Y=Y, mode="x3"))
+        ms_vec = timed(lambda: [H.matvec(c, y=yv) for c in cols])
+        Y6 = H.matmat(X, mode="x6").cpu().numpy()
+        Y3 = H.matmat(X, mode="x3").cpu().numpy()
+        Yv = np.stack([H.matvec(c).cpu().numpy() for c in cols], axis=1)
+        entries = info["dense_entries"] + info["lr_entries"]
+        H.close()
+        torch.cuda.empty_cache()
+        r6 = float(np.linalg.norm(Y6 - Yv) / np.linalg.norm(Yv))
+        r3 = float(np.linalg.norm(Y3 - Yv) / np.linalg.norm(Yv))
+        res = {"N": f.n, "members": 64, "factor_bytes": info["factor_bytes"],
+               "ms_mfma_bf16x6": ms_x6, "ms_mfma_bf16x3": ms_x3, "ms_64_fp32_matvecs": ms_vec,
+               "speedup_x6_vs_64_matvecs": ms_vec / ms_x6, "speedup_x3_vs_64_matvecs": ms_vec / ms_x3,
+               "member_products_per_s_x6": 64e3 / ms_x6,
+               "mfma_tflops_x6": 6 * 2 * entries * 64 / (ms_x6 * 1e-3) / 1e12,
+               "mfma_util_x6": 6 * 2 * entries * 64 / (ms_x6 * 1e-3) / 2.5e15,
+               "factor_gbs_x6": info["factor_bytes"] / (ms_x6 * 1e-3) / 1e9,
+               "rel_diff_x6_vs_fp32_matvecs": r6, "rel_diff_x3_vs_fp32_matvecs": r3}
+        log(f"[bench] ensemble {name}: x6 {ms_x6:.3f} ms, x3 {ms_x3:.3f} ms, 64 matvecs {ms_vec:.3f} ms "
+            f"(x{ms_vec / ms_x6:.1f}), rel x6 {r6:.1e} x3 {r3:.1e}")
+        out[name] = res
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +245,8 @@ def main():
     ap.add_argument("--variants", default="batched_f32,plain_f64,batched_f64")
     ap.add_argument("--rk-steps", type=int, default=50,
                     help="accepted RK45 steps of the rate-and-state simulation on the same fault (0: skip)")
+    ap.add_argument("--ensemble", default="dip30_150x140,dip30_480x256",
+                    help="workloads of the 64-member MFMA ensemble product ('' to skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -298,6 +359,8 @@ def main():
         line["rel_diff_f32_vs_f64_gpu"] = float(np.linalg.norm(outputs["batched_f32"] - ref) / np.linalg.norm(ref))
     if args.rk_steps > 0:
         line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
+    if args.ensemble:
+        line["ensemble"] = ensemble(torch, hm, args.ensemble.split(","))
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
         line["cpu_baseline"] = cpu_baseline(f, w, x_np, outputs["batched_f32"])
