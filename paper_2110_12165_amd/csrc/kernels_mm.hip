@@ -10,9 +10,11 @@
 // cross products with i + j < NS are accumulated in FP32:
 //   NS = 2: p0q0 + p0q1 + p1q0              (3 products, "BF16x3")
 //   NS = 3: ... + p0q2 + p1q1 + p2q0         (6 products, "BF16x6")
-// The members' values are kept split and in cluster order (member-major,
-// input-contiguous), so a unit's inputs are staged into LDS by contiguous
-// copies; the panels are split on the fly as they stream from HBM.
+// The members' values are kept split, in cluster order, member-contiguous
+// ([part][input][64]), so staging one input moves 16-byte chunks of 8
+// members; LDS holds them input-contiguous per member ([part][member][k]),
+// the order the MFMA operand wants.  The panels are split on the fly as they
+// stream from HBM.
 #include <hip/hip_runtime.h>
 
 #include "device_types.hpp"
@@ -41,31 +43,20 @@ __device__ __forceinline__ void split(float x, __bf16* p) {
   }
 }
 
-// Member values of the inputs: Xs[p][r][k] (cluster order k < n), parts p < NS.
+// Member values of the inputs, split: Xs[p][k][r] (cluster order k < n).
 template <int NS>
 __global__ __launch_bounds__(256) void k_split_members(int64_t n, int nrhs, const double* __restrict__ X,
                                                        int64_t ldx, const int32_t* __restrict__ perm,
                                                        __bf16* __restrict__ Xs) {
-  // 64 x 64 tile: read member-contiguous rows, write input-contiguous rows
-  __shared__ float tile[64][65];
-  const int64_t k0 = (int64_t)blockIdx.x * 64;
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;  // 64 x 4
-  for (int j = ty; j < 64; j += 4) {
-    const int64_t k = k0 + j;
-    float v = 0.f;
-    if (k < n && tx < nrhs) v = (float)X[(int64_t)perm[k] * ldx + tx];
-    tile[j][tx] = v;
-  }
-  __syncthreads();
-  for (int r = ty; r < kNR; r += 4) {
-    const int64_t k = k0 + tx;
-    if (k < n) {
-      __bf16 p[NS];
-      split<NS>(tile[tx][r], p);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (k, r)
+  if (e >= n * kNR) return;
+  const int64_t k = e / kNR;
+  const int r = (int)(e % kNR);
+  const float v = r < nrhs ? (float)X[(int64_t)perm[k] * ldx + r] : 0.f;
+  __bf16 p[NS];
+  split<NS>(v, p);
 #pragma unroll
-      for (int i = 0; i < NS; ++i) Xs[((int64_t)i * kNR + r) * n + k] = p[i];
-    }
-  }
+  for (int i = 0; i < NS; ++i) Xs[((int64_t)i * n + k) * kNR + r] = p[i];
 }
 
 // MT: output tiles of 16 per wave (phase-2 units have at most 64 outputs: 1).
@@ -87,21 +78,27 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
     for (int j = 0; j < 4; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   for (int c0 = 0; c0 < K; c0 += kKS) {
-    // stage inputs c0 .. c0+kKS of every member and part (zero beyond K)
-    for (int e = tid; e < NS * kNR * kKS; e += kWaves * 64) {
-      const int kk = e % kKS, r = (e / kKS) % kNR, p = e / (kKS * kNR);
+    // stage inputs c0 .. c0+kKS: items (part, input, 8-member chunk), one
+    // 16-byte load each, scattered into LDS input-contiguous per member
+    for (int e = tid; e < NS * kKS * 8; e += kWaves * 64) {
+      const int ch = e & 7, kk = (e >> 3) % kKS, p = e / (8 * kKS);
       const int k = c0 + kk;
-      __bf16 v = (__bf16)0.f;
+      s16x8 v = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
       if (k < K) {
+        const s16x8* srcp = nullptr;
         if (PHASE == 1) {
-          if (k < u.nin) v = Xs[((int64_t)p * kNR + r) * a.n + u.in0 + k];
+          if (k < u.nin) srcp = reinterpret_cast<const s16x8*>(Xs + (((int64_t)p * a.n + u.in0 + k) * kNR + 8 * ch));
         } else {
           const int s = a.src[u.in0 + k];
-          if (s >= 0) v = Xs[((int64_t)p * kNR + r) * a.n + a.invperm[s]];
-          else if (s < -1) v = Ts[((int64_t)p * kNR + r) * a.t_size + (-s - 1)];
+          if (s >= 0)
+            srcp = reinterpret_cast<const s16x8*>(Xs + (((int64_t)p * a.n + a.invperm[s]) * kNR + 8 * ch));
+          else if (s < -1)
+            srcp = reinterpret_cast<const s16x8*>(Ts + (((int64_t)p * a.t_size + (-s - 1)) * kNR + 8 * ch));
         }
+        if (srcp) v = *srcp;
       }
-      zs[p][r][kk] = v;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) zs[p][8 * ch + j][kk] = __builtin_bit_cast(__bf16, v[j]);
     }
     __syncthreads();
 #pragma unroll
@@ -167,7 +164,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
           split<NS>(v, pp);
           const int64_t slot = (int64_t)u.out0 + o;
 #pragma unroll
-          for (int p = 0; p < NS; ++p) Ts[((int64_t)p * kNR + r) * a.t_size + slot] = pp[p];
+          for (int p = 0; p < NS; ++p) Ts[((int64_t)p * a.t_size + slot) * kNR + r] = pp[p];
         } else if (r < a.nrhs) {
           double* yp = a.Y + (int64_t)a.perm[u.out0 + o] * a.ldy + r;
           *yp = beta == 0.0 ? alpha * (double)v : fma(alpha, (double)v, beta * *yp);
@@ -181,8 +178,8 @@ template <int NS>
 hipError_t launch_ns(const MMArgs& a, double alpha, double beta, hipStream_t s, hipEvent_t* ev) {
   const int64_t n = a.n;
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL((k_split_members<NS>), dim3((unsigned)((n + 63) / 64)), dim3(256), 0, s, n, a.nrhs, a.X, a.ldx,
-                     a.perm, static_cast<__bf16*>(a.Xs));
+  hipLaunchKernelGGL((k_split_members<NS>), dim3((unsigned)((n * kNR + 255) / 256)), dim3(256), 0, s, n, a.nrhs, a.X,
+                     a.ldx, a.perm, static_cast<__bf16*>(a.Xs));
   if (a.n1 > 0) hipLaunchKernelGGL((k_mm<NS, 1, 4>), dim3(a.n1), dim3(kWaves * 64), 0, s, a, alpha, beta);
   if (ev) (void)hipEventRecord(ev[1], s);
   if (a.n2 > 0) hipLaunchKernelGGL((k_mm<NS, 2, 1>), dim3(a.n2), dim3(kWaves * 64), 0, s, a, alpha, beta);

@@ -15,8 +15,8 @@ struct MMArgs {
   const int32_t* perm;     // cluster position -> user element
   const int32_t* invperm;  // user element -> cluster position
   int64_t n, t_size;
-  void* Xs;                // bf16 [3][64][n]: split member values, cluster order
-  void* Ts;                // bf16 [3][64][t_size]: split intermediate values
+  void* Xs;                // bf16 [3][n][64]: split member values, cluster order
+  void* Ts;                // bf16 [3][t_size][64]: split intermediate values
   const double* X;         // user order, element-major: X[i * ldx + r]
   int64_t ldx;
   double* Y;               // user order, element-major: Y[i * ldy + r]
