@@ -64,7 +64,8 @@ template <int NS, int PHASE, int MT>
 __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, double beta) {
   const __bf16* __restrict__ Xs = static_cast<const __bf16*>(a.Xs);
   __bf16* Ts = static_cast<__bf16*>(a.Ts);
-  __shared__ __attribute__((aligned(16))) __bf16 zs[NS][kNR][kLd];
+  // bf16 bit patterns as 16-bit integers (whole vectors are bit-cast to bf16)
+  __shared__ __attribute__((aligned(16))) unsigned short zs[NS][kNR][kLd];
   const Unit u = a.units[(PHASE == 1 ? 0 : a.n1) + blockIdx.x];
   const float* pool = static_cast<const float*>(a.pool);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
@@ -98,7 +99,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
         if (srcp) v = *srcp;
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) zs[p][8 * ch + j][kk] = __builtin_bit_cast(__bf16, v[j]);
+      for (int j = 0; j < 8; ++j) zs[p][8 * ch + j][kk] = (unsigned short)v[j];
     }
     __syncthreads();
 #pragma unroll
