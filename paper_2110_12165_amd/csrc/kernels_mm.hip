@@ -32,6 +32,12 @@ constexpr int kKS = 128;      // inputs staged per round (K)
 constexpr int kLd = kKS + 8;  // LDS row pitch in bf16 (pad against bank conflicts)
 constexpr int kWaves = 4;
 
+// LDS column of input kk in member row r: 16-byte chunks of 8 inputs are
+// XOR-swizzled by the row group (r / 8) so that the eight rows written by one
+// staged 16-byte load fall into different banks; an MFMA operand read (8
+// consecutive inputs of one row) stays one aligned 16-byte chunk.
+__device__ __forceinline__ int zcol(int r, int kk) { return (((kk >> 3) ^ ((r >> 3) & 7)) << 3) | (kk & 7); }
+
 template <int NS>
 __device__ __forceinline__ void split(float x, __bf16* p) {
   float r = x;
@@ -99,7 +105,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
         if (srcp) v = *srcp;
       }
 #pragma unroll
-      for (int j = 0; j < 8; ++j) zs[p][8 * ch + j][kk] = (unsigned short)v[j];
+      for (int j = 0; j < 8; ++j) zs[p][8 * ch + j][zcol(8 * ch + j, kk)] = (unsigned short)v[j];
     }
     __syncthreads();
 #pragma unroll
@@ -136,7 +142,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
           bf16x8 bp[NS];
 #pragma unroll
           for (int i = 0; i < NS; ++i)
-            bp[i] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const s16x8*>(&zs[i][nt * 16 + lm][ks + 8 * lk]));
+            bp[i] = __builtin_bit_cast(
+                bf16x8, *reinterpret_cast<const s16x8*>(&zs[i][nt * 16 + lm][zcol(nt * 16 + lm, ks + 8 * lk)]));
 #pragma unroll
           for (int i = 0; i < NS; ++i)
 #pragma unroll
