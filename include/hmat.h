@@ -111,6 +111,8 @@ typedef struct {
                               0 = default (4) */
   int32_t max_nrhs;        /* > 0: allocate the buffers of hmat_matmat at creation (needs
                               HMAT_F32, a BATCHED kernel and wg_waves_p1 <= 4); 0: none */
+  int32_t transpose;       /* 1: also lay out H^T for hmat_matvec_T (doubles the factor
+                              storage); 0: hmat_matvec_T returns HMAT_ESTATE */
 } hmat_opts;
 
 /* Arithmetic of hmat_matmat: FP32 factors and member values are split into
@@ -121,7 +123,8 @@ typedef enum {
   HMAT_MM_BF16X6 = 3       /* 3 parts (exact FP32), 6 products: FP32-level accuracy */
 } hmat_mm_mode;
 
-/* Fill *opts with defaults (eps 1e-6, eta 2, leaf 32, lattice 1, FP64, AUTO). */
+/* Fill *opts with defaults (eps 1e-6, eta 2, leaf 32, lattice 1, FP64, AUTO,
+ * transpose 1). */
 void hmat_default_opts(hmat_opts* opts);
 
 /* Statistics of a handle (hmat_info). */
@@ -221,7 +224,9 @@ hmat_status hmat_export(hmat_t h, hmat_host_blocks* out);
 hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld,
                         double alpha, double beta, void* stream);
 
-/* hmat_matvec_T — y = alpha * H^T x + beta * y; same arguments and rules. */
+/* hmat_matvec_T — y = alpha * H^T x + beta * y; same arguments and rules.
+ * Runs the product kernels on the packed blocks of H^T (dense blocks
+ * transposed, U and V exchanged); needs a handle created with transpose = 1. */
 
 /*
  * hmat_matmat — Y = alpha * H X + beta * Y for nrhs members at once

@@ -73,6 +73,9 @@ struct hmat_s {
   int32_t* d_perm = nullptr;
   hm::PlainArgs plain{};
   hm::BatchedArgs batched{};
+  hm::BatchedArgs batched_t{};       // layout of H^T (hmat_matvec_T), if built
+  bool has_plain = false, has_batched_t = false;
+  int grid_t = 0;
   int grid = 0;
   int cus = 0;
   int32_t* d_invperm = nullptr;  // ensemble product: user element -> cluster position
@@ -163,8 +166,8 @@ struct hmat_s {
   }
 
   template <typename T>
-  void setup_plain(hipStream_t s) {
-    hm::PlainLayout<T> L = hm::make_plain<T>(H, true);
+  void setup_plain(bool transpose, hipStream_t s) {
+    hm::PlainLayout<T> L = hm::make_plain<T>(H, transpose);
     plain.blocks = upload(L.blocks, s);
     plain.lr_list = upload(L.lr_list, s);
     plain.n_lr = (int32_t)L.lr_list.size();
@@ -179,6 +182,26 @@ struct hmat_s {
     plain.t = alloc_zero<double>((size_t)std::max<int64_t>(1, L.sum_rank), s);
     st.sum_rank = L.sum_rank;
     st.n_leaves = (int64_t)L.row_units.size();
+    has_plain = true;
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+  }
+
+  // Batched layout of H^T, kept for the life of the handle (fixed set).
+  template <typename T>
+  void setup_batched_t(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
+    hm::BatchedLayout<T> L = hm::make_batched<T>(hm::transpose_host(H), wg, unit_bytes, wg1);
+    batched_t.units = upload(L.units, s);
+    batched_t.n1 = L.n1;
+    batched_t.n2 = L.n2;
+    batched_t.src = upload(L.src, s);
+    batched_t.t = alloc_zero<double>((size_t)L.t_size, s);
+    batched_t.pool = upload(L.pool, s);
+    batched_t.perm = d_perm;
+    batched_t.ctr = alloc_zero<hm::QueueCounters>(1, s);
+    batched_t.wg_waves = wg;
+    batched_t.wg_waves_p1 = wg1;
+    grid_t = hm::persistent_blocks_per_cu<T>(wg) * cus;
+    has_batched_t = true;
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
   }
 
@@ -221,12 +244,19 @@ struct hmat_s {
     else setup_batched<double>(wg, unit_bytes, wg1, s);
   }
 
+  // transpose: H^T, through its batched layout when built, else the natural
+  // layout's column units.
   hipError_t product(bool transpose, const double* x, double* y, double alpha, double beta, hipStream_t s,
                      int32_t kern, hipEvent_t* ev = nullptr) const {
-    if (transpose || kern == HMAT_KERNEL_PLAIN)
+    const bool pers = kern == HMAT_KERNEL_BATCHED_PERSISTENT;
+    if (transpose && has_batched_t)
+      return f32() ? hm::launch_batched<float>(batched_t, pers, grid_t, x, y, alpha, beta, s, ev)
+                   : hm::launch_batched<double>(batched_t, pers, grid_t, x, y, alpha, beta, s, ev);
+    if (transpose || kern == HMAT_KERNEL_PLAIN) {
+      if (!has_plain || (transpose && plain.n_cols == 0)) return hipErrorInvalidValue;
       return f32() ? hm::launch_plain<float>(plain, transpose, x, y, alpha, beta, s, ev)
                    : hm::launch_plain<double>(plain, transpose, x, y, alpha, beta, s, ev);
-    const bool pers = kern == HMAT_KERNEL_BATCHED_PERSISTENT;
+    }
     return f32() ? hm::launch_batched<float>(batched, pers, grid, x, y, alpha, beta, s, ev)
                  : hm::launch_batched<double>(batched, pers, grid, x, y, alpha, beta, s, ev);
   }
@@ -251,6 +281,7 @@ void check_opts(const hmat_opts& o, bool build) {
     hm::fail(HMAT_EINVAL, "wg_waves_p1 must be 0, 4, 8 or 16");
   if (o.unit_kib < 0) hm::fail(HMAT_EINVAL, "unit_kib must be >= 0");
   if (o.max_nrhs < 0) hm::fail(HMAT_EINVAL, "max_nrhs must be >= 0");
+  if (o.transpose != 0 && o.transpose != 1) hm::fail(HMAT_EINVAL, "transpose must be 0 or 1");
 }
 
 // Default schedule of the batched product (fastest measured on MI355X for
@@ -288,13 +319,24 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
   h->rs_x = h->alloc_zero<double>((size_t)n, s);
   h->rs_ax = h->alloc_zero<double>((size_t)n, s);
   h->rs_bx = h->alloc_zero<double>((size_t)n, s);
-  if (h->f32()) h->setup_plain<float>(s);
-  else h->setup_plain<double>(s);
-  if (h->kernel != HMAT_KERNEL_PLAIN) {
+  if (h->kernel == HMAT_KERNEL_PLAIN) {
+    if (h->f32()) h->setup_plain<float>(o.transpose != 0, s);
+    else h->setup_plain<double>(o.transpose != 0, s);
+  } else {
     const int32_t wg = o.wg_waves ? o.wg_waves : kDefaultWaves;
     const int32_t wg1 = o.wg_waves_p1 ? o.wg_waves_p1 : kDefaultWavesP1;
     const int64_t ub = (int64_t)(o.unit_kib ? o.unit_kib : kDefaultUnitKiB) * 1024;
     h->setup_batched_any(wg, ub, wg1, s);
+    if (o.transpose) {
+      const int32_t w1 = h->kernel == HMAT_KERNEL_BATCHED_PERSISTENT ? wg : wg1;
+      if (h->f32()) h->setup_batched_t<float>(wg, ub, w1, s);
+      else h->setup_batched_t<double>(wg, ub, w1, s);
+    }
+    // intermediate-vector length and row units of the product (statistics)
+    int64_t sr = 0;
+    for (int64_t b = 0; b < h->H.nblocks(); ++b) sr += h->H.desc[6 * b + 5];
+    h->st.sum_rank = sr;
+    h->st.n_leaves = (int64_t)hm::refine_ranges(h->H, false, 64).size();
   }
   fill_stats(h.get());
   return h.release();
@@ -364,6 +406,7 @@ void hmat_default_opts(hmat_opts* o) {
   o->max_rank = 0;
   o->prec = HMAT_F64;
   o->kernel = HMAT_KERNEL_AUTO;
+  o->transpose = 1;
 }
 
 hmat_status hmat_build(const hmat_mesh* mesh, const hmat_green* green, const hmat_opts* opts, void* stream,
@@ -453,8 +496,11 @@ hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, in
     if (nrhs == 0) return;
     DeviceGuard g(h->device);
     const hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!h->has_batched_t && !(h->has_plain && h->plain.n_cols > 0))
+      hm::fail(HMAT_ESTATE, "handle created without opts.transpose");
+    const int32_t kt = h->kernel == HMAT_KERNEL_PLAIN ? HMAT_KERNEL_PLAIN : h->kernel;
     for (int64_t c = 0; c < nrhs; ++c)
-      check_hip(h->product(true, x + c * ld, y + c * ld, alpha, beta, s, HMAT_KERNEL_PLAIN), "transpose launch");
+      check_hip(h->product(true, x + c * ld, y + c * ld, alpha, beta, s, kt), "transpose launch");
   });
 }
 
@@ -535,9 +581,10 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
       check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
       return (double)ms / reps;
     };
-    double best = time_it(HMAT_KERNEL_PLAIN);
-    int32_t best_k = HMAT_KERNEL_PLAIN, best_w = 0, best_u = 0;
-    int32_t best_w1 = 0;
+    double best = h->has_plain ? time_it(HMAT_KERNEL_PLAIN) : 1e300;
+    int32_t best_k = h->has_plain ? HMAT_KERNEL_PLAIN : h->kernel, best_w = h->opts.wg_waves,
+            best_u = kDefaultUnitKiB;
+    int32_t best_w1 = h->opts.wg_waves_p1;
     const int32_t saved_kernel = h->kernel;
     for (int32_t k : {HMAT_KERNEL_BATCHED_SPLIT, HMAT_KERNEL_BATCHED_PERSISTENT})
       for (int32_t wg : {4, 8, 16})

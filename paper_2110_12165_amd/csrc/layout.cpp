@@ -66,6 +66,39 @@ std::vector<std::pair<int64_t, int64_t>> refine_ranges(const HostMatrix& H, bool
   return out;
 }
 
+HostMatrix transpose_host(const HostMatrix& H) {
+  HostMatrix T;
+  T.n = H.n;
+  T.perm = H.perm;
+  T.lattice = H.lattice;
+  T.tree_depth = H.tree_depth;
+  const int64_t nb = H.nblocks();
+  T.desc.resize(6 * nb);
+  T.off = H.off;
+  T.values.resize(H.values.size());
+  for (int64_t b = 0; b < nb; ++b) {
+    const int64_t* d = &H.desc[6 * b];
+    int64_t* e = &T.desc[6 * b];
+    const int64_t m = d[2], n = d[4], r = d[5];
+    e[0] = d[0];
+    e[1] = d[3];
+    e[2] = n;
+    e[3] = d[1];
+    e[4] = m;
+    e[5] = r;
+    const double* v = &H.values[H.off[b]];
+    double* w = &T.values[H.off[b]];
+    if (d[0] == 0) {
+      for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < m; ++i) w[i * n + j] = v[j * m + i];  // D^T, column-major n x m
+    } else {
+      std::copy(v + m * r, v + (m + n) * r, w);      // U' = V (n x r)
+      std::copy(v, v + m * r, w + n * r);            // V' = U (m x r)
+    }
+  }
+  return T;
+}
+
 template <typename T>
 PlainLayout<T> make_plain(const HostMatrix& H, bool transpose) {
   PlainLayout<T> L;

@@ -44,6 +44,10 @@ struct BatchedLayout {
 template <typename T>
 BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1);
 
+// The blocks of H^T (dense blocks transposed, U and V exchanged), same
+// permutation: packing them gives the layouts of the transpose product.
+HostMatrix transpose_host(const HostMatrix& H);
+
 // Row intervals of the finest common refinement of the blocks' row (or
 // column) ranges, each split into pieces of at most `cap` rows.
 std::vector<std::pair<int64_t, int64_t>> refine_ranges(const HostMatrix& H, bool columns, int64_t cap);

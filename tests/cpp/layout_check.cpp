@@ -177,6 +177,30 @@ int main(int argc, char** argv) {
     }
   }
   for (int64_t i = 0; i < n; ++i) yref[H.perm[i]] = yc[i];
+  // transpose: direct product with H^T over the original blocks
+  std::vector<double> yrefT(n, 0.0), ycT(n, 0.0);
+  for (int64_t b = 0; b < H.nblocks(); ++b) {
+    const int64_t* d = &H.desc[6 * b];
+    const double* v = &H.values[H.off[b]];
+    if (d[0] == 0) {
+      for (int64_t j = 0; j < d[4]; ++j)
+        for (int64_t i = 0; i < d[2]; ++i) ycT[d[3] + j] += v[j * d[2] + i] * x[H.perm[d[1] + i]];
+    } else {
+      for (int64_t k = 0; k < d[5]; ++k) {
+        double sk = 0.0;
+        for (int64_t i = 0; i < d[2]; ++i) sk += v[k * d[2] + i] * x[H.perm[d[1] + i]];
+        for (int64_t j = 0; j < d[4]; ++j) ycT[d[3] + j] += v[d[2] * d[5] + k * d[4] + j] * sk;
+      }
+    }
+  }
+  for (int64_t i = 0; i < n; ++i) yrefT[H.perm[i]] = ycT[i];
+  const HostMatrix HT = transpose_host(H);
+  for (int NW : {4, 8}) {
+    const double r64 = replay<double>(HT, NW, 4, 256 << 10, x, yrefT);
+    const double r32 = replay<float>(HT, NW, 4, 256 << 10, x, yrefT);
+    std::printf("transpose NW=%d rel64=%.3e rel32=%.3e\n", NW, r64, r32);
+    if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed transpose product differs");
+  }
   for (int NW : {4, 8, 16})
     for (int NW1 : {4, 8, 16})
     for (int64_t ub : {64 << 10, 4 << 20}) {
