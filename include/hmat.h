@@ -344,13 +344,57 @@ hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, d
  * A, re-captured when any argument changes) and replayed.
  * max_attempts > 0 bounds the attempts (HMAT_ESTATE if the target is not
  * reached; the state stays consistent).  st is updated on return.
+ * dt_log: DEVICE, n_accept doubles, or NULL; entry m receives the step of
+ * the m-th step accepted by this call (the list rs_rk45_replay takes).
  */
 hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
-                        rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, int32_t use_graph, void* stream);
+                        rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, double* dt_log,
+                        int32_t use_graph, void* stream);
 
 /* rs_rk45_step — rs_rk45_run for one accepted step, without a graph. */
 hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                          rs_rk45_state* st, int32_t max_attempts, void* stream);
+
+/*
+ * rs_rk45_replay — the integration of rs_rk45_run on a frozen list of steps
+ * (section 2.2 stages, eq. (16) slip; no error control: every step is taken).
+ * Replaying the dt_log of a controlled run reproduces that run.
+ *   y: DEVICE 3n, advanced in place; D: DEVICE n slip, accumulated, or NULL.
+ *   dts: HOST, n_steps steps (> 0, finite).
+ *   ckpt: DEVICE, ceil(n_steps / ckpt_every) * 3n doubles, or NULL; block c
+ *     receives y before step c * ckpt_every (the checkpoints rs_rk45_adjoint
+ *     starts its segments from).
+ *   workspace: DEVICE, rs_rk45_workspace_bytes(n), 8-byte aligned.
+ *   Asynchronous on `stream`; allocates nothing.
+ */
+hmat_status rs_rk45_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const double* dts,
+                           int64_t n_steps, double* ckpt, int64_t ckpt_every, void* workspace, void* stream);
+
+/* Bytes of device workspace rs_rk45_adjoint needs: 8 (36 n K + 31 n + 32)
+ * with K = min(ckpt_every, n_steps) (-1 on bad arguments or overflow). */
+int64_t rs_rk45_adjoint_workspace_bytes(int64_t n, int64_t ckpt_every);
+
+/*
+ * rs_rk45_adjoint — reverse-mode derivative of rs_rk45_replay (the discrete
+ * adjoint of the frozen-step integration).  For a loss L(y_M, D_M) of the
+ * state and slip after the n_steps steps, given Dbar = dL/dD_M and
+ * ybar = dL/dy_M, it returns dL/dy_0 in y_bar and adds dL/da and dL/dd_c to
+ * a_bar and dc_bar (b held fixed, so dL/da is also the derivative with
+ * respect to a - b).  Each segment of ckpt_every steps is recomputed from its
+ * checkpoint with every stage kept, then swept backwards: per stage one
+ * product with A^T (and B^T), eqs. (8), (12), (13) differentiated element by
+ * element.  The handles need transposed products (opts.transpose, or the
+ * plain kernel), else HMAT_ESTATE.
+ *   ckpt: DEVICE, as written by rs_rk45_replay with the same ckpt_every, dts.
+ *   D_bar: DEVICE n, or NULL (zero).  y_bar: DEVICE 3n, in dL/dy_M, out dL/dy_0.
+ *   a_bar, dc_bar: DEVICE n, accumulated (+=).
+ *   workspace: DEVICE, at least rs_rk45_adjoint_workspace_bytes(n,
+ *     min(ckpt_every, n_steps)) bytes (workspace_bytes), 8-byte aligned.
+ *   Asynchronous on `stream`; allocates nothing.
+ */
+hmat_status rs_rk45_adjoint(hmat_t A, hmat_t B, const rs_params* p, const double* ckpt, int64_t ckpt_every,
+                            const double* dts, int64_t n_steps, const double* D_bar, double* y_bar, double* a_bar,
+                            double* dc_bar, void* workspace, int64_t workspace_bytes, void* stream);
 
 /* Release the handle and all its device memory (NULL is ignored).
  * Synchronises the device first. */

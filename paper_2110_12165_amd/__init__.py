@@ -265,14 +265,73 @@ class RK45:
                                _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), max_attempts,
                                _stream_ptr(stream)))
 
-    def run(self, y, D, n_accept, max_attempts=0, use_graph=True, stream=None):
+    def run(self, y, D, n_accept, max_attempts=0, use_graph=True, stream=None, dt_log=None):
         """Advance n_accept accepted steps with the step control on the GPU
-        (rs_rk45_run).  The graph path needs a non-default stream."""
+        (rs_rk45_run).  The graph path needs a non-default stream.  dt_log:
+        optional float64 GPU tensor of n_accept entries receiving the
+        accepted steps (the list replay() and adjoint() take)."""
         self._check(y, D)
+        if dt_log is not None and (dt_log.dtype != _torch().float64 or not dt_log.is_cuda
+                                   or dt_log.numel() < n_accept or not dt_log.is_contiguous()):
+            raise ValueError("dt_log must be a contiguous float64 GPU tensor of at least n_accept entries")
         lib = _lib.load()
         check(lib.rs_rk45_run(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
                               _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), n_accept,
-                              max_attempts, 1 if use_graph else 0, _stream_ptr(stream)))
+                              max_attempts, None if dt_log is None else _dptr(dt_log), 1 if use_graph else 0,
+                              _stream_ptr(stream)))
+
+    def replay(self, y, D, dts, ckpt_every=0, stream=None):
+        """The integration on the frozen steps dts (rs_rk45_replay): y (and D,
+        unless None) advance in place.  With ckpt_every > 0 returns the
+        checkpoints (the state before every ckpt_every-th step) for adjoint()."""
+        torch = _torch()
+        n = self.A.n
+        if y.shape != (3 * n,) or y.dtype != torch.float64 or not y.is_contiguous():
+            raise ValueError("y must be a contiguous (3n,) float64 GPU tensor")
+        if D is not None and (D.shape != (n,) or D.dtype != torch.float64 or not D.is_contiguous()):
+            raise ValueError("D must be a contiguous (n,) float64 GPU tensor")
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        m = d.shape[0]
+        ckpt = None
+        if ckpt_every > 0:
+            ckpt = torch.empty(((m + ckpt_every - 1) // ckpt_every) * 3 * n, dtype=torch.float64, device=y.device)
+        check(_lib.load().rs_rk45_replay(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
+                                         _dptr(y), None if D is None else _dptr(D),
+                                         d.ctypes.data_as(C.POINTER(C.c_double)), m,
+                                         None if ckpt is None else _dptr(ckpt), max(ckpt_every, 1),
+                                         _dptr(self.workspace), _stream_ptr(stream)))
+        return ckpt
+
+    def adjoint(self, ckpt, dts, ckpt_every, y_bar, D_bar=None, a_bar=None, dc_bar=None, stream=None):
+        """Reverse sweep of replay() (rs_rk45_adjoint).  y_bar: dL/dy_M on
+        entry, dL/dy_0 on return (in place); D_bar: dL/dD_M or None.
+        a_bar, dc_bar accumulate dL/da and dL/dd_c (new zero tensors when
+        None).  Returns (y_bar, a_bar, dc_bar)."""
+        torch = _torch()
+        n = self.A.n
+        d = np.ascontiguousarray(dts, dtype=np.float64)
+        m = d.shape[0]
+        dev = y_bar.device
+        if a_bar is None:
+            a_bar = torch.zeros(n, dtype=torch.float64, device=dev)
+        if dc_bar is None:
+            dc_bar = torch.zeros(n, dtype=torch.float64, device=dev)
+        for t, k in ((y_bar, 3 * n), (a_bar, n), (dc_bar, n)) + (() if D_bar is None else ((D_bar, n),)):
+            if t.shape != (k,) or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("cotangents must be contiguous float64 GPU tensors of length 3n (state) or n")
+        lib = _lib.load()
+        nbytes = lib.rs_rk45_adjoint_workspace_bytes(n, max(1, min(ckpt_every, m)))
+        if nbytes < 0:
+            raise ValueError("bad adjoint sizes")
+        if getattr(self, "_adj_ws", None) is None or self._adj_ws.numel() * 8 < nbytes:
+            self._adj_ws = torch.empty(nbytes // 8, dtype=torch.float64, device=dev)
+        check(lib.rs_rk45_adjoint(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
+                                  None if ckpt is None else _dptr(ckpt), ckpt_every,
+                                  d.ctypes.data_as(C.POINTER(C.c_double)), m,
+                                  None if D_bar is None else _dptr(D_bar), _dptr(y_bar), _dptr(a_bar),
+                                  _dptr(dc_bar), _dptr(self._adj_ws), self._adj_ws.numel() * 8,
+                                  _stream_ptr(stream)))
+        return y_bar, a_bar, dc_bar
 
     @property
     def t(self):

@@ -86,7 +86,13 @@ SIGNATURES = {
     "rs_rk45_attempt": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.POINTER(RsRk45State), C.c_int32, C.c_void_p]),
     "rs_rk45_run": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
-                              C.POINTER(RsRk45State), C.c_int64, C.c_int64, C.c_int32, C.c_void_p]),
+                              C.POINTER(RsRk45State), C.c_int64, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+    "rs_rk45_replay": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p,
+                                 C.POINTER(C.c_double), C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "rs_rk45_adjoint_workspace_bytes": (C.c_int64, [C.c_int64, C.c_int64]),
+    "rs_rk45_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_int64,
+                                  C.POINTER(C.c_double), C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_int64, C.c_void_p]),
     "rs_rk45_step": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.POINTER(RsRk45State), C.c_int32, C.c_void_p]),
     "hmat_destroy": (None, [C.c_void_p]),

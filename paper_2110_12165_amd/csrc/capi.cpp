@@ -16,6 +16,7 @@
 #include "kernels_mm.hpp"
 #include "layout.hpp"
 #include "rs.hpp"
+#include "rs_adjoint.hpp"
 
 namespace {
 
@@ -93,9 +94,9 @@ struct hmat_s {
   std::vector<const void*> rk_key;
 
   template <typename F>
-  void rk_graph(hmat_t B, const rs_params* p, const double* y, const double* D, const void* ws, hipStream_t s,
-                F&& enqueue) {
-    std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, ws, s};
+  void rk_graph(hmat_t B, const rs_params* p, const double* y, const double* D, const void* ws, const double* dt_log,
+                hipStream_t s, F&& enqueue) {
+    std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, ws, dt_log, s};
     const double consts[4] = {p->V0, p->f0, p->eta_rad, p->V_pl};
     for (double c : consts) {
       const void* v;
@@ -726,7 +727,8 @@ void check_rk_args(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D,
 }
 
 // Enqueue one attempt: every kernel reads the step from the device state.
-void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const RkWs& w, hipStream_t s) {
+void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const RkWs& w, double* dt_log,
+                     hipStream_t s) {
   const int64_t n = A->H.n, n3 = 3 * n;
   check_hip(hm::launch_rk_begin(w.st, s), "rk begin launch");
   for (int stage = 0; stage < 6; ++stage) {
@@ -742,7 +744,7 @@ void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* 
     check_hip(hm::launch_rs_rhs(n, *p, yin, w.ax, B ? w.bx : nullptr, w.k + stage * n3, s), "rhs launch");
   }
   check_hip(hm::launch_rk_finish_control(n3, w.st, y, w.k, w.y5, s), "error launch");
-  check_hip(hm::launch_rk_accept(n, w.st, p->V0, p->a, w.y5, w.Vs, y, D, s), "accept launch");
+  check_hip(hm::launch_rk_accept(n, w.st, p->V0, p->a, w.y5, w.Vs, y, D, dt_log, s), "accept launch");
 }
 
 void put_state(const RkWs& w, const rs_rk45_state* st, long long target, int force, hipStream_t s) {
@@ -754,6 +756,7 @@ void put_state(const RkWs& w, const rs_rk45_state* st, long long target, int for
   d.rejected = st->rejected;
   d.target = target;
   d.force = force;
+  d.log_base = st->accepted;
   check_hip(hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
   check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
 }
@@ -780,13 +783,14 @@ hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, d
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const RkWs w = rk_workspace(workspace, A->H.n);
     put_state(w, st, st->accepted + 1, force, s);
-    enqueue_attempt(A, B, p, y, D, w, s);
+    enqueue_attempt(A, B, p, y, D, w, nullptr, s);
     get_state(w, st, s);
   });
 }
 
 hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
-                        rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, int32_t use_graph, void* stream) {
+                        rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, double* dt_log, int32_t use_graph,
+                        void* stream) {
   return guarded([&] {
     check_rk_args(A, B, p, y, D, workspace, st);
     if (n_accept < 0 || max_attempts < 0) hm::fail(HMAT_EINVAL, "counts must be >= 0");
@@ -797,7 +801,9 @@ hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, doubl
     const long long target = st->accepted + n_accept;
     put_state(w, st, target, -1, s);
     const bool graph = use_graph && s != nullptr;
-    if (graph) A->rk_graph(B, p, y, D, workspace, s, [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, cs); });
+    if (graph)
+      A->rk_graph(B, p, y, D, workspace, dt_log, s,
+                  [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, dt_log, cs); });
     int64_t launched = 0;
     for (;;) {
       int64_t batch = target - st->accepted;
@@ -805,7 +811,7 @@ hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, doubl
       if (batch <= 0) break;
       for (int64_t k = 0; k < batch; ++k) {
         if (graph) check_hip(hipGraphLaunch(A->rk_exec, s), "hipGraphLaunch");
-        else enqueue_attempt(A, B, p, y, D, w, s);
+        else enqueue_attempt(A, B, p, y, D, w, dt_log, s);
       }
       launched += batch;
       get_state(w, st, s);
@@ -818,7 +824,145 @@ hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, doubl
 hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                          rs_rk45_state* st, int32_t max_attempts, void* stream) {
   if (max_attempts < 1) return set_err(HMAT_EINVAL, "max_attempts must be >= 1");
-  return rs_rk45_run(A, B, p, y, D, workspace, st, 1, max_attempts, 0, stream);
+  return rs_rk45_run(A, B, p, y, D, workspace, st, 1, max_attempts, nullptr, 0, stream);
+}
+
+namespace {
+
+void check_replay_args(hmat_t A, hmat_t B, const rs_params* p, const double* dts, int64_t n_steps,
+                       int64_t ckpt_every) {
+  if (!A || !p) hm::fail(HMAT_EINVAL, "null argument");
+  if (!A->on_device || (B && !B->on_device)) hm::fail(HMAT_ESTATE, "handle holds host blocks only");
+  if (p->n != A->H.n || (B && B->H.n != A->H.n)) hm::fail(HMAT_EINVAL, "n does not match the handles");
+  if (B && B->device != A->device) hm::fail(HMAT_EINVAL, "A and B live on different devices");
+  if (!p->a || !p->b || !p->dc) hm::fail(HMAT_EINVAL, "null friction parameter array");
+  if (!(p->V0 > 0.0) || !(p->eta_rad >= 0.0) || !std::isfinite(p->f0) || !std::isfinite(p->V_pl))
+    hm::fail(HMAT_EINVAL, "bad friction constants");
+  if (n_steps < 0) hm::fail(HMAT_EINVAL, "n_steps must be >= 0");
+  if (ckpt_every < 1) hm::fail(HMAT_EINVAL, "ckpt_every must be >= 1");
+  if (n_steps > 0 && !dts) hm::fail(HMAT_EINVAL, "null step list");
+  for (int64_t m = 0; m < n_steps; ++m)
+    if (!(dts[m] > 0.0) || !std::isfinite(dts[m])) hm::fail(HMAT_EINVAL, "steps must be positive and finite");
+}
+
+// One step of the frozen-step integration from y_in to y_out (may alias):
+// the six stages write their derivatives to K (6 blocks of 3n) and, when
+// Ystore is given, their inputs for stages 1..5 to Ystore (5 blocks of 3n);
+// otherwise the stage input goes to ys.  x, ax, bx: n-vectors.
+void enqueue_frozen_step(hmat_t A, hmat_t B, const rs_params* p, const double* y_in, double* y_out, double* D,
+                         double dt, double* K, double* Ystore, double* ys, double* x, double* ax, double* bx,
+                         hipStream_t s) {
+  const int64_t n = A->H.n, n3 = 3 * n;
+  for (int stage = 0; stage < 6; ++stage) {
+    const double* yin = y_in;
+    if (stage > 0) {
+      double* dst = Ystore ? Ystore + (stage - 1) * n3 : ys;
+      check_hip(hm::launch_rk_stage_dt(n3, stage, dt, y_in, K, dst, s), "stage launch");
+      yin = dst;
+    }
+    check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, yin, x, nullptr, s), "slip-rate launch");
+    check_hip(A->product(false, x, ax, 1.0, 0.0, s, A->kernel), "product launch");
+    if (B) check_hip(B->product(false, x, bx, 1.0, 0.0, s, B->kernel), "product launch");
+    check_hip(hm::launch_rs_rhs(n, *p, yin, ax, B ? bx : nullptr, K + stage * n3, s), "rhs launch");
+  }
+  check_hip(hm::launch_rk_update_dt(n, dt, p->V0, p->a, K, y_in, y_out, D, s), "update launch");
+}
+
+bool transposable(hmat_t h) { return h->has_batched_t || (h->has_plain && h->plain.n_cols > 0); }
+
+}  // namespace
+
+hmat_status rs_rk45_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const double* dts,
+                           int64_t n_steps, double* ckpt, int64_t ckpt_every, void* workspace, void* stream) {
+  return guarded([&] {
+    check_replay_args(A, B, p, dts, n_steps, ckpt_every);
+    if (!y || !workspace) hm::fail(HMAT_EINVAL, "null argument");
+    if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
+    if (n_steps == 0) return;
+    DeviceGuard g(A->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = A->H.n, n3 = 3 * n;
+    double* K = static_cast<double*>(workspace);  // 18n, then ys 3n, x, ax, bx
+    double* ys = K + 6 * n3;
+    double* x = ys + n3;
+    double* ax = x + n;
+    double* bx = ax + n;
+    for (int64_t m = 0; m < n_steps; ++m) {
+      if (ckpt && m % ckpt_every == 0)
+        check_hip(hipMemcpyAsync(ckpt + (m / ckpt_every) * n3, y, n3 * sizeof(double), hipMemcpyDeviceToDevice, s),
+                  "checkpoint copy");
+      enqueue_frozen_step(A, B, p, y, y, D, dts[m], K, nullptr, ys, x, ax, bx, s);
+    }
+  });
+}
+
+int64_t rs_rk45_adjoint_workspace_bytes(int64_t n, int64_t ckpt_every) {
+  if (n < 0 || ckpt_every < 1) return -1;
+  if (n > 0 && ckpt_every > (INT64_MAX / 8 - 64) / (36 * n) - 1) return -1;
+  return 8 * (36 * n * ckpt_every + 31 * n + 32);
+}
+
+hmat_status rs_rk45_adjoint(hmat_t A, hmat_t B, const rs_params* p, const double* ckpt, int64_t ckpt_every,
+                            const double* dts, int64_t n_steps, const double* D_bar, double* y_bar, double* a_bar,
+                            double* dc_bar, void* workspace, int64_t workspace_bytes, void* stream) {
+  return guarded([&] {
+    check_replay_args(A, B, p, dts, n_steps, ckpt_every);
+    if (!y_bar || !a_bar || !dc_bar || !workspace || (n_steps > 0 && !ckpt)) hm::fail(HMAT_EINVAL, "null argument");
+    if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
+    const int64_t n = A->H.n, n3 = 3 * n;
+    const int64_t K = std::min<int64_t>(ckpt_every, std::max<int64_t>(n_steps, 1));
+    const int64_t need = rs_rk45_adjoint_workspace_bytes(n, K);
+    if (need < 0 || workspace_bytes < need) hm::fail(HMAT_EINVAL, "workspace too small");
+    if (!transposable(A) || (B && !transposable(B)))
+      hm::fail(HMAT_ESTATE, "handle created without opts.transpose");
+    if (n_steps == 0) return;
+    DeviceGuard g(A->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    double* states = static_cast<double*>(workspace);  // (K + 1) 3n
+    double* Ys = states + (K + 1) * n3;                // K x 5 x 3n stage inputs 1..5
+    double* Ks = Ys + K * 5 * n3;                      // K x 6 x 3n stage derivatives
+    double* Ybar = Ks + K * 6 * n3;                    // 6 x 3n
+    double* kbar = Ybar + 6 * n3;                      // 3n
+    double* gbar = kbar + n3;
+    double* sbar = gbar + n;
+    double* xa = sbar + n;
+    double* xb = xa + n;
+    double* x = xb + n;
+    double* ax = x + n;
+    double* bx = ax + n;
+    const int64_t nseg = (n_steps + ckpt_every - 1) / ckpt_every;
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+      const int64_t m0 = seg * ckpt_every, L = std::min(ckpt_every, n_steps - m0);
+      // recompute the segment from its checkpoint, keeping every stage
+      check_hip(hipMemcpyAsync(states, ckpt + seg * n3, n3 * sizeof(double), hipMemcpyDeviceToDevice, s),
+                "checkpoint copy");
+      for (int64_t l = 0; l < L; ++l)
+        enqueue_frozen_step(A, B, p, states + l * n3, states + (l + 1) * n3, nullptr, dts[m0 + l], Ks + l * 6 * n3,
+                            Ys + l * 5 * n3, nullptr, x, ax, bx, s);
+      // reverse sweep over the segment
+      for (int64_t l = L - 1; l >= 0; --l) {
+        const double dt = dts[m0 + l];
+        if (D_bar)
+          check_hip(hm::launch_adj_dterm(n, 0.5 * dt, p->V0, p->a, states + (l + 1) * n3, D_bar, y_bar, a_bar, s),
+                    "slip-term launch");
+        for (int r = 5; r >= 0; --r) {
+          const double* Yr = r == 0 ? states + l * n3 : Ys + (l * 5 + r - 1) * n3;
+          const double* Kr = Ks + (l * 6 + r) * n3;
+          check_hip(hm::launch_adj_vjp_pre(n, r, dt, *p, Yr, y_bar, Ybar, kbar, gbar, B ? sbar : nullptr, s),
+                    "adjoint stage launch");
+          check_hip(A->product(true, gbar, xa, 1.0, 0.0, s, A->kernel), "transpose launch");
+          if (B) check_hip(B->product(true, sbar, xb, 1.0, 0.0, s, B->kernel), "transpose launch");
+          check_hip(hm::launch_adj_vjp_post(n, *p, Yr, Kr, kbar, xa, B ? xb : nullptr, Ybar + r * n3, a_bar, dc_bar,
+                                            s),
+                    "adjoint stage launch");
+        }
+        check_hip(hm::launch_adj_combine(n3, y_bar, Ybar, s), "adjoint combine launch");
+        if (D_bar)
+          check_hip(hm::launch_adj_dterm(n, 0.5 * dt, p->V0, p->a, states + l * n3, D_bar, y_bar, a_bar, s),
+                    "slip-term launch");
+      }
+    }
+  });
 }
 
 void hmat_destroy(hmat_t h) { delete h; }

@@ -50,18 +50,4 @@ struct QueueCounters {
   uint32_t next, p1done, exited, pad;
 };
 
-// Device-resident state of the adaptive Runge-Kutta integration: every
-// kernel of an attempt reads the step from here, and the controller kernel
-// (eqs. (14)-(15)) updates it, so attempts can be replayed from a graph with
-// no host round trip.
-struct RkDevState {
-  double t, dt, eps, r, dt_used;
-  long long accepted, rejected, target;
-  int force;        // -1 controller decides, 0 reject, 1 accept
-  int ok;           // decision of the last attempt
-  int halted;       // target reached: further attempts change nothing
-  int pad;
-  unsigned long long err_bits;  // max relative difference, as the bits of a non-negative double
-};
-
 }  // namespace hm

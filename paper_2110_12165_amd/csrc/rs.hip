@@ -16,6 +16,8 @@
 // The backslip loading tau_dot = -V_pl sum_j A_ij is folded into the product
 // by applying A to V - V_pl.
 #include "device_types.hpp"
+#include "rk_state.hpp"
+#include "rk_tableau.hpp"
 #include "rs.hpp"
 
 namespace hm {
@@ -61,16 +63,6 @@ __global__ void k_rhs(int64_t n, double V0, double f0, double eta, const double*
 // relative difference of the two solutions (section 2.2) and the accepted
 // update with the trapezoidal slip rule of eq. (16).
 // ---------------------------------------------------------------------------
-__constant__ double kA[6][5] = {
-    {0, 0, 0, 0, 0},
-    {1.0 / 5.0, 0, 0, 0, 0},
-    {3.0 / 40.0, 9.0 / 40.0, 0, 0, 0},
-    {3.0 / 10.0, -9.0 / 10.0, 6.0 / 5.0, 0, 0},
-    {-11.0 / 54.0, 5.0 / 2.0, -70.0 / 27.0, 35.0 / 27.0, 0},
-    {1631.0 / 55296.0, 175.0 / 512.0, 575.0 / 13824.0, 44275.0 / 110592.0, 253.0 / 4096.0}};
-__constant__ double kB5[6] = {37.0 / 378.0, 0.0, 250.0 / 621.0, 125.0 / 594.0, 0.0, 512.0 / 1771.0};
-__constant__ double kB4[6] = {2825.0 / 27648.0, 0.0, 18575.0 / 48384.0, 13525.0 / 55296.0, 277.0 / 14336.0, 0.25};
-
 // ys = y + dt * sum_{j<s} a_sj k_j
 __global__ void k_stage(int64_t n3, int s, const RkDevState* __restrict__ st, const double* __restrict__ y,
                         const double* __restrict__ k, double* __restrict__ ys) {
@@ -154,10 +146,11 @@ __global__ void k_control(RkDevState* st) {
 // accepted step: D += dt/2 (V(y) + V(y5)) (eq. 16); y = y5
 __global__ void k_accept(int64_t n, const RkDevState* __restrict__ st, double V0, const double* __restrict__ a,
                          const double* __restrict__ y5, const double* __restrict__ Vstart, double* __restrict__ y,
-                         double* __restrict__ D) {
+                         double* __restrict__ D, double* __restrict__ dt_log) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n || !st->ok) return;
   const double dt = st->dt_used;
+  if (dt_log && i == 0) dt_log[st->accepted - 1 - st->log_base] = dt;
   const double phi = y5[i], tau = y5[n + i], sig = y5[2 * n + i];
   const double ai = a[i];
   const double q = tau / (ai * sig), e = phi / ai;
@@ -191,10 +184,10 @@ hipError_t launch_rk_finish_control(int64_t n3, RkDevState* st, const double* y,
 }
 
 hipError_t launch_rk_accept(int64_t n, const RkDevState* st, double V0, const double* a, const double* y5,
-                            const double* Vstart, double* y, double* D, hipStream_t strm) {
+                            const double* Vstart, double* y, double* D, double* dt_log, hipStream_t strm) {
   const int bs = 256;
   hipLaunchKernelGGL(k_accept, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, strm, n, st, V0, a, y5, Vstart, y,
-                     D);
+                     D, dt_log);
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "device_types.hpp"
+#include "rk_state.hpp"
 #include "hmat.h"
 
 namespace hm {
@@ -28,8 +29,9 @@ hipError_t launch_rk_stage(int64_t n3, int s, const RkDevState* st, const double
 // y5, the largest relative difference |y5 - y4| / |y5| and the step control.
 hipError_t launch_rk_finish_control(int64_t n3, RkDevState* st, const double* y, const double* k, double* y5,
                                     hipStream_t strm);
-// accepted step (if the controller accepted): eq. (16) slip update, y = y5.
+// accepted step (if the controller accepted): eq. (16) slip update, y = y5;
+// dt_log (or null) receives the step at index accepted - 1 - log_base.
 hipError_t launch_rk_accept(int64_t n, const RkDevState* st, double V0, const double* a, const double* y5,
-                            const double* Vstart, double* y, double* D, hipStream_t strm);
+                            const double* Vstart, double* y, double* D, double* dt_log, hipStream_t strm);
 
 }  // namespace hm

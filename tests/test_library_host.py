@@ -130,7 +130,18 @@ def test_invalid_arguments_rejected(lib):
     st, h = _host_build(lib, f, w)
     assert st == 0
     assert so.hmat_matvec(h, C.c_void_p(16), C.c_void_p(1 << 20), 1, 64, 1.0, 0.0, None) == -4
+    # the frozen-step integration and its adjoint check the handle first
+    prm = lib.RsParams(64, 1e-6, 0.6, 4.6e6, 1e-9, 16, 16, 16)
+    dts = (C.c_double * 3)(1.0, 2.0, 4.0)
+    assert so.rs_rk45_replay(h, None, C.byref(prm), C.c_void_p(16), None, dts, 3, None, 1, C.c_void_p(16), None) == -4
+    assert so.rs_rk45_adjoint(h, None, C.byref(prm), C.c_void_p(16), 2, dts, 3, None, C.c_void_p(16),
+                              C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), 1 << 30, None) == -4
     so.hmat_destroy(h)
+    # workspace of the adjoint: 8 (36 n K + 31 n + 32) bytes
+    assert so.rs_rk45_adjoint_workspace_bytes(1000, 50) == 8 * (36 * 1000 * 50 + 31 * 1000 + 32)
+    assert so.rs_rk45_adjoint_workspace_bytes(-1, 50) == -1
+    assert so.rs_rk45_adjoint_workspace_bytes(10, 0) == -1
+    assert so.rs_rk45_adjoint_workspace_bytes(1 << 30, 1 << 30) == -1
 
 
 def test_import_validates_tiling(lib):
