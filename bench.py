@@ -236,6 +236,92 @@ def ensemble(torch, hm, workloads, reps=20):
     return out
 
 
+def adjoint_run(torch, hm, n_steps, ckpt_every=50):
+    """Gradient of the final-slip misfit L = 1/2 |D_M - D_target|^2 for
+    per-element a (b fixed) and d_c on the N = 21000 mesh with FP32 factors:
+    a controlled run logs its n_steps accepted steps; the target slip comes
+    from a perturbed by U(-1e-3, 1e-3) (seed 4), integrated with its own step
+    control to the same final time; then the timed part: the frozen-step
+    replay writing checkpoints every ckpt_every steps, and the adjoint sweep
+    (segments recomputed from their checkpoints, one A^T product per stage)."""
+    from synth import WORKLOADS, config_fault, friction_params
+    from synth.faults import MU, NU
+
+    name = "dip30_150x140"
+    w = WORKLOADS[name]
+    f = config_fault(name)
+    p = friction_params(f)
+    n = f.n
+    dev = torch.device("cuda:0")
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
+                         lattice=w["lattice"], prec="f32", kernel="split")
+    a, b, dc = (torch.tensor(p[k], device=dev) for k in ("a", "b", "dc"))
+    # steady state at log-uniform slip rates (seed 3), state variable kicked by U(-0.05, 0.05)
+    V = 10.0 ** (-12.0 + 3.0 * np.random.default_rng(3).random(n))
+    phi = p["f0"] + p["b"] * np.log(p["V0"] / V) + np.random.default_rng(103).uniform(-0.05, 0.05, n)
+    tau = p["a"] * p["sigma"] * np.arcsinh(V / (2 * p["V0"]) * np.exp(phi / p["a"]))
+    y0 = np.concatenate([phi, tau, p["sigma"]])
+    consts = (p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    rk = hm.RK45(H, None, a, b, dc, *consts)
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(n, dtype=torch.float64, device=dev)
+    log_dt = torch.zeros(n_steps, dtype=torch.float64, device=dev)
+    rk.run(y, D, n_steps, use_graph=False, dt_log=log_dt)
+    dts = log_dt.cpu().numpy()
+    T = rk.t
+    at = a + torch.tensor(np.random.default_rng(4).uniform(-1e-3, 1e-3, n), device=dev)
+    rkt = hm.RK45(H, None, at, b, dc, *consts)
+    yt = torch.tensor(y0, device=dev)
+    D_t = torch.zeros(n, dtype=torch.float64, device=dev)
+    while rkt.t + rkt.dt < T:
+        rkt.step(yt, D_t)
+    rkt.dt = T - rkt.t
+    rkt.attempt(yt, D_t, force=1)
+    # warm-up of the timed calls (also sizes the adjoint workspace)
+    yw = torch.tensor(y0, device=dev)
+    ck = rk.replay(yw, None, dts[:ckpt_every], ckpt_every=ckpt_every)
+    rk.adjoint(ck, dts[:ckpt_every], ckpt_every, torch.zeros_like(yw))
+    torch.cuda.synchronize()
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(n, dtype=torch.float64, device=dev)
+    t0 = time.perf_counter()
+    ckpt = rk.replay(y, D, dts, ckpt_every=ckpt_every)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    Dbar = D - D_t
+    ybar = torch.zeros_like(y)
+    _, ga, gdc = rk.adjoint(ckpt, dts, ckpt_every, ybar, Dbar)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    x = torch.tensor(V, device=dev)
+    yv = torch.empty_like(x)
+    prof = H.profile(x, yv, reps=20)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(3):
+        H.matvec_T(x, y=yv)
+    e0.record()
+    for _ in range(20):
+        H.matvec_T(x, y=yv)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_t = e0.elapsed_time(e1) / 20
+    fwd, bwd = t1 - t0, t2 - t1
+    prod_s = (12 * n_steps * prof["ms_product"] + 6 * n_steps * ms_t) * 1e-3
+    H.close()
+    torch.cuda.empty_cache()
+    loss = 0.5 * float((Dbar * Dbar).sum())
+    log(f"[bench] adjoint: N={n}, {n_steps} steps to t={T:.3e} s, forward {fwd:.3f} s, adjoint {bwd:.3f} s, "
+        f"L={loss:.3e}")
+    return {"workload": name, "N": n, "steps": n_steps, "ckpt_every": ckpt_every, "factor_storage": "f32",
+            "simulated_s": T, "forward_replay_s": fwd, "adjoint_s": bwd, "gradient_s": fwd + bwd,
+            "products": 18 * n_steps, "ms_product": prof["ms_product"], "ms_product_T": ms_t,
+            "hmvm_share": prod_s / (fwd + bwd), "loss": loss,
+            "grad_a_norm": float(ga.norm()), "grad_dc_norm": float(gdc.norm()),
+            "note": "L = 1/2 |D_M - D_target|^2; D_target from a + U(-1e-3, 1e-3) (seed 4) by its own step control "
+                    "to the same final time; gradient by the discrete adjoint of the frozen-step replay; "
+                    "products: 6 per step forward, 6 per step recomputed from checkpoints, 6 transposed"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +333,8 @@ def main():
                     help="accepted RK45 steps of the rate-and-state simulation on the same fault (0: skip)")
     ap.add_argument("--ensemble", default="dip30_150x140,dip30_480x256",
                     help="workloads of the 64-member MFMA ensemble product ('' to skip)")
+    ap.add_argument("--adjoint-steps", type=int, default=500,
+                    help="steps of the adjoint section (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
@@ -361,6 +449,8 @@ def main():
         line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
     if args.ensemble:
         line["ensemble"] = ensemble(torch, hm, args.ensemble.split(","))
+    if args.adjoint_steps > 0:
+        line["adjoint"] = adjoint_run(torch, hm, args.adjoint_steps)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
         line["cpu_baseline"] = cpu_baseline(f, w, x_np, outputs["batched_f32"])

@@ -5,8 +5,14 @@ central finite differences of the GPU forward map at the size of the
 paper-scale ensemble mesh.
 
 Loss: L = 1/2 |D_M - D_target|^2, D_target from a perturbed by
-U(-1e-3, 1e-3) (seed 4) on the same frozen steps; gradients for a (b fixed:
-also the gradient for a - b), d_c and the initial state.
+U(-1e-3, 1e-3) (seed 4): on the same frozen steps for the small case, by
+its own controlled integration to the same final time for the paper-scale
+case; gradients for a (b fixed: also the gradient for a - b), d_c and the
+initial state.
+
+The paper-scale check (N = 21000, FP32 factors, 20 elements of seed 4)
+covers the steps before nucleation; the full 500-step window of the
+benchmark, which runs through a seismic event, is timed by bench.py.
 
 Tolerances.  Shared FP64 factors: the products agree with the oracle's to
 1e-13 and the element-wise functions to a few ulp; over 20 steps the
@@ -168,11 +174,34 @@ def test_autograd_function(small):
     assert _close(dc.grad.cpu().numpy() - gdc_c.cpu().numpy(), gdc_r) <= tol
 
 
+def _target_at(hm, Hg, p, a, b, dc, y0, T):
+    """Slip at time T of the controlled integration with parameters (a, b,
+    dc): steps while they end before T, then one forced step to T."""
+    import torch
+    rk = hm.RK45(Hg, None, a, b, dc, p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    y = torch.tensor(y0, device=a.device)
+    D = torch.zeros(len(y0) // 3, dtype=torch.float64, device=a.device)
+    while rk.t + rk.dt < T:
+        rk.step(y, D)
+    rk.dt = T - rk.t
+    rk.attempt(y, D, force=1)
+    return D, rk.state.accepted
+
+
+WINDOW = 80   # steps of the controlled run before nucleation (slip rates stay below 1e-8 m/s)
+
+
 @pytest.fixture(scope="module")
 def paper_scale():
     """N = 21000 planar stand-in of the paper-scale mesh, FP32 factors, built
-    by the library; 500 steps of the controlled run from a kicked steady
-    state, their steps logged."""
+    by the library; the first WINDOW steps of the controlled run from a kicked
+    steady state, their steps logged.  Later steps of this run nucleate and
+    host a seismic event, through which the final slip is so sensitive to a
+    (gradients ~1e10) that a central difference of one element's a by 1e-6
+    already leaves the frozen steps' stability region.  The target slip comes
+    from the perturbed a at the same final time, by its own controlled
+    integration: the frozen steps of the base run sit at the explicit
+    stability limit, which a 10 % change of a moves."""
     import torch
 
     import paper_2110_12165_amd as hm
@@ -188,26 +217,26 @@ def paper_scale():
     rk = hm.RK45(Hg, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
     y = torch.tensor(y0, device=dev)
     D = torch.zeros(f.n, dtype=torch.float64, device=dev)
-    log = torch.zeros(500, dtype=torch.float64, device=dev)
-    rk.run(y, D, 500, use_graph=False, dt_log=log)
+    log = torch.zeros(WINDOW, dtype=torch.float64, device=dev)
+    rk.run(y, D, WINDOW, use_graph=False, dt_log=log)
     dts = log.cpu().numpy()
-    at = dp["a"] + torch.tensor(np.random.default_rng(4).uniform(-1e-3, 1e-3, f.n), device=dev)
-    rkt = hm.RK45(Hg, None, at, dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
-    yt = torch.tensor(y0, device=dev)
-    D_t = torch.zeros_like(D)
-    rkt.replay(yt, D_t, dts)
-    say(f"[paper scale] N={f.n}, 500 steps, t={rk.t:.3e} s, rejected {rk.state.rejected}, "
-        f"largest slip {float(D.max()):.3e} m")
+    n = f.n
+    yn = y.cpu().numpy()
+    vmax = float(np.max(fr.slip_rate(yn[:n], yn[n:2 * n], yn[2 * n:], p["a"], p["V0"])))
+    at = dp["a"] + torch.tensor(np.random.default_rng(4).uniform(-1e-3, 1e-3, n), device=dev)
+    D_t, steps_t = _target_at(hm, Hg, p, at, dp["b"], dp["dc"], y0, rk.t)
+    say(f"[paper scale] N={n}, {WINDOW} steps to t={rk.t:.4e} s ({rk.state.rejected} rejected), largest slip "
+        f"{float(D.max()):.3e} m, largest slip rate {vmax:.2e} m/s; target: {steps_t} steps, "
+        f"largest slip {float(D_t.max()):.3e} m")
+    assert vmax < 1e-8 and torch.isfinite(D_t).all()
     yield torch, hm, f, p, Hg, dp, y0, dts, D_t
     Hg.close()
 
 
-@pytest.mark.skip(reason="the 500-step window of this initial state contains a seismic event: the frozen steps "
-                         "are unstable for the perturbed target (NaN); window being redefined")
 def test_adjoint_against_central_differences_paper_scale(paper_scale):
     torch, hm, f, p, Hg, dp, y0, dts, D_t = paper_scale
     dev = dp["a"].device
-    say("[adjoint vs FD] dip30_150x140 f32, 500 steps, ckpt 50, 20 elements")
+    say(f"[adjoint vs FD] dip30_150x140 f32, {WINDOW} steps, ckpt 50, 20 elements")
     rk = hm.RK45(Hg, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
     y = torch.tensor(y0, device=dev)
     D = torch.zeros(f.n, dtype=torch.float64, device=dev)
@@ -237,5 +266,6 @@ def test_adjoint_against_central_differences_paper_scale(paper_scale):
             fd = (loss(*args_p) - loss(*args_m)) / (2 * h)
             err = abs(fd - g[i]) / (abs(g[i]) + 1e-2 * scale)
             worst = max(worst, err)
+            say(f"   {key}[{int(i)}]: adjoint {g[i]: .6e}  central difference {fd: .6e}")
             assert abs(fd - g[i]) <= 1e-4 * abs(g[i]) + 1e-6 * scale, (key, int(i), fd, g[i])
     say(f"   worst FD mismatch (relative): {worst:.2e}")
