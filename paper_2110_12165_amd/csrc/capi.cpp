@@ -84,6 +84,8 @@ struct hmat_s {
   void* mm_ts = nullptr;         // ensemble product: bf16 [3][64][t_size]
   int64_t t_size = 0;
   int32_t max_nout_p1 = 0;
+  int32_t* mm_slices1 = nullptr;  // ensemble product: 64-output slices of the phase-1 units
+  int32_t mm_ns1 = 0;
   double* rs_x = nullptr;  // n doubles: slip rate minus plate rate (rs_rhs scratch)
   double* rs_ax = nullptr;  // n doubles: A (V - V_pl)
   double* rs_bx = nullptr;  // n doubles: B (V - V_pl)
@@ -226,6 +228,11 @@ struct hmat_s {
       if (opts.prec != HMAT_F32) hm::fail(HMAT_EUNSUPPORTED, "the ensemble product needs FP32 storage");
       if (max_nout_p1 > 256) hm::fail(HMAT_EUNSUPPORTED, "the ensemble product needs wg_waves_p1 <= 4");
       mm_ts = alloc_zero<uint16_t>((size_t)3 * 64 * L.t_size, s, true);
+      std::vector<int32_t> sl;
+      for (int32_t i = 0; i < L.n1; ++i)
+        for (int32_t k = 0; 64 * k < L.units[i].nout; ++k) sl.push_back(4 * i + k);
+      mm_ns1 = (int32_t)sl.size();
+      if (!sl.empty()) mm_slices1 = upload(sl, s, true);
     }
     grid = hm::persistent_blocks_per_cu<T>(wg) * cus;
     st.n_units_p1 = L.n1;
@@ -528,6 +535,8 @@ hmat_status hmat_matmat(hmat_t h, const double* X, int64_t ldx, double* Y, int64
       a.units = h->batched.units;
       a.n1 = h->batched.n1;
       a.n2 = h->batched.n2;
+      a.slices1 = h->mm_slices1;
+      a.ns1 = h->mm_ns1;
       a.src = h->batched.src;
       a.pool = h->batched.pool;
       a.perm = h->d_perm;

@@ -11,10 +11,11 @@
 //   NS = 2: p0q0 + p0q1 + p1q0              (3 products, "BF16x3")
 //   NS = 3: ... + p0q2 + p1q1 + p2q0         (6 products, "BF16x6")
 // The members' values are kept split, in cluster order, member-contiguous
-// ([part][input][64]), so staging one input moves 16-byte chunks of 8
-// members; LDS holds them input-contiguous per member ([part][member][k]),
-// the order the MFMA operand wants.  The panels are split on the fly as they
-// stream from HBM.
+// ([part][input][64]), and are staged into LDS unchanged (16-byte copies):
+// one LDS row per input, 64 members.  The MFMA B operand wants 8 consecutive
+// inputs of one member per lane; gfx950's transposing LDS read
+// (ds_read_b64_tr_b16) delivers exactly that from member-contiguous rows.
+// The panels are split on the fly as they stream from HBM.
 #include <hip/hip_runtime.h>
 
 #include "device_types.hpp"
@@ -28,15 +29,36 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kNR = 64;       // members per product (N)
-constexpr int kKS = 128;      // inputs staged per round (K)
-constexpr int kLd = kKS + 8;  // LDS row pitch in bf16 (pad against bank conflicts)
+constexpr int kKS = 64;       // inputs staged per round (K)
 constexpr int kWaves = 4;
 
-// LDS column of input kk in member row r: 16-byte chunks of 8 inputs are
-// XOR-swizzled by the row group (r / 8) so that the eight rows written by one
-// staged 16-byte load fall into different banks; an MFMA operand read (8
-// consecutive inputs of one row) stays one aligned 16-byte chunk.
-__device__ __forceinline__ int zcol(int r, int kk) { return (((kk >> 3) ^ ((r >> 3) & 7)) << 3) | (kk & 7); }
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+
+// Physical 16-byte chunk (8 members) of member chunk ch in LDS row r.  The
+// XOR with row bits 1 and 3 makes both the staging writes (two rows of eight
+// chunks per 16 lanes) and the transposing reads (four rows of two chunks per
+// 16 lanes, two such groups per half-wave) free of bank conflicts.
+__device__ __forceinline__ int zchunk(int r, int ch) { return ch ^ (r & 2) ^ ((r >> 1) & 4); }
+
+// B fragment of v_mfma_f32_16x16x32_bf16 for inputs k0 + [0, 32) and members
+// m0 + [0, 16) from member-contiguous LDS rows: lane l receives inputs
+// k0 + 8 (l / 16) + [0, 8) of member m0 + l % 16.  ds_read_b64_tr_b16 gives
+// lane i of a 16-lane group element i % 4 of the 4-element vectors addressed
+// by lanes 4e + i / 4 (e = 0..3, one per result element), so lane j of the
+// group addresses input row (j / 4) and members 4 (j % 4) + [0, 4).
+__device__ __forceinline__ s16x8 b_fragment(const unsigned short (*z)[kNR], int k0, int m0, int lane) {
+  const int g = lane >> 4, j = lane & 15;
+  const int col = m0 + 4 * (j & 3);
+  s16x4 h[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int row = k0 + 8 * g + 4 * t + (j >> 2);
+    const unsigned short* p = &z[row][8 * zchunk(row, col >> 3) + (col & 7)];
+    h[t] = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p));
+  }
+  return s16x8{h[0][0], h[0][1], h[0][2], h[0][3], h[1][0], h[1][1], h[1][2], h[1][3]};
+}
 
 template <int NS>
 __device__ __forceinline__ void split(float x, __bf16* p) {
@@ -65,75 +87,125 @@ __global__ __launch_bounds__(256) void k_split_members(int64_t n, int nrhs, cons
   for (int i = 0; i < NS; ++i) Xs[((int64_t)i * n + k) * kNR + r] = p[i];
 }
 
-// MT: output tiles of 16 per wave (phase-2 units have at most 64 outputs: 1).
-template <int NS, int PHASE, int MT>
-__global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, double beta) {
+constexpr int kItems = kKS * 8 / (kWaves * 64);  // 16-byte staging items per thread and part
+
+// Members of inputs c0 + [0, kKS) of a unit, split parts, read into registers
+// (item e = tid + 256 i: input e / 8, 8-member chunk e % 8); zero beyond the
+// unit's inputs and for the zero pad of the intermediate vector.
+template <int NS, int PHASE>
+__device__ __forceinline__ void stage_load(const MMArgs& a, const Unit& u, int c0, int K, int tid,
+                                           s16x8 (&sr)[NS][kItems]) {
   const __bf16* __restrict__ Xs = static_cast<const __bf16*>(a.Xs);
+  const __bf16* Ts = static_cast<const __bf16*>(a.Ts);
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int e = tid + it * kWaves * 64;
+    const int ch = e & 7, k = c0 + (e >> 3);
+    const __bf16* row = nullptr;
+    int64_t part = 0;
+    if (k < K) {
+      if (PHASE == 1) {
+        if (k < u.nin) {
+          row = Xs + ((int64_t)u.in0 + k) * kNR;
+          part = a.n * kNR;
+        }
+      } else {
+        const int sx = a.src[u.in0 + k];
+        if (sx >= 0) {
+          row = Xs + (int64_t)a.invperm[sx] * kNR;
+          part = a.n * kNR;
+        } else if (sx < -1) {
+          row = Ts + (int64_t)(-sx - 1) * kNR;
+          part = a.t_size * kNR;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+      sr[p][it] = row ? *reinterpret_cast<const s16x8*>(row + p * part + 8 * ch) : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  }
+}
+
+template <int NS>
+__device__ __forceinline__ void stage_store(unsigned short (*zs)[kKS][kNR], int tid, const s16x8 (&sr)[NS][kItems]) {
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int e = tid + it * kWaves * 64;
+    const int ch = e & 7, kk = e >> 3;
+#pragma unroll
+    for (int p = 0; p < NS; ++p) *reinterpret_cast<s16x8*>(&zs[p][kk][8 * zchunk(kk, ch)]) = sr[p][it];
+  }
+}
+
+// Panel quads of output o for the four 32-input steps of the round at c0:
+// step s, half h = quad (c0 + 32 s) / 4 + 2 lk + h.
+__device__ __forceinline__ void load_a(const float* pool, const Unit& u, int c0, int o, bool orow, int lk,
+                                       f32x4 (&ar)[kKS / 32][2]) {
+#pragma unroll
+  for (int st = 0; st < kKS / 32; ++st)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = (c0 + 32 * st) / 4 + 2 * lk + h;
+      ar[st][h] = (orow && q < u.nq) ? __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(
+                                           pool + u.off + ((size_t)q * u.nout + o) * 4))
+                                     : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+}
+
+// One workgroup per 64-output slice of a unit (phase-1 units with more than
+// 64 outputs are split into slices that stage the same inputs); wave w owns
+// the 16 outputs 16 w + [0, 16) of the slice and all 64 members.  Rounds are
+// software-pipelined: the members and panel quads of the next round are
+// loaded into registers while the MFMAs of the current round run, and
+// written to LDS after it.
+template <int NS, int PHASE>
+__global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, double beta) {
   __bf16* Ts = static_cast<__bf16*>(a.Ts);
-  // bf16 bit patterns as 16-bit integers (whole vectors are bit-cast to bf16)
-  __shared__ __attribute__((aligned(16))) unsigned short zs[NS][kNR][kLd];
-  const Unit u = a.units[(PHASE == 1 ? 0 : a.n1) + blockIdx.x];
+  // bf16 bit patterns as 16-bit integers (whole vectors are bit-cast to bf16);
+  // row = input of the round, 64 members, chunks swizzled by zchunk
+  __shared__ __attribute__((aligned(16))) unsigned short zs[NS][kKS][kNR];
+  int ui, ob = 0;
+  if (PHASE == 1) {
+    const int code = a.slices1[blockIdx.x];
+    ui = code >> 2;
+    ob = 64 * (code & 3);
+  } else {
+    ui = a.n1 + blockIdx.x;
+  }
+  const Unit u = a.units[ui];
   const float* pool = static_cast<const float*>(a.pool);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int lm = lane & 15, lk = lane >> 4;  // MFMA lane: row/col within 16, k group of 8
-  const int ntiles = (u.nout + 15) >> 4;     // 16-output tiles, up to MT per wave
+  const int ntiles = (min(u.nout, ob + 64) - ob + 15) >> 4;
   const int K = u.nq * 4;
-  f32x4 acc[MT][4];
+  const int rounds = (K + kKS - 1) / kKS;
+  const int o = ob + wave * 16 + lm;
+  const bool work = wave < ntiles, orow = work && o < u.nout;
+  f32x4 acc[4];
 #pragma unroll
-  for (int t = 0; t < MT; ++t)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[t][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  s16x8 sr[NS][kItems];
+  f32x4 ar[kKS / 32][2], an[kKS / 32][2];
+  stage_load<NS, PHASE>(a, u, 0, K, tid, sr);
+  if (work) load_a(pool, u, 0, o, orow, lk, ar);
+  stage_store<NS>(zs, tid, sr);
+  __syncthreads();
 
-  for (int c0 = 0; c0 < K; c0 += kKS) {
-    // stage inputs c0 .. c0+kKS: items (part, input, 8-member chunk), one
-    // 16-byte load each, scattered into LDS input-contiguous per member
-    for (int e = tid; e < NS * kKS * 8; e += kWaves * 64) {
-      const int ch = e & 7, kk = (e >> 3) % kKS, p = e / (8 * kKS);
-      const int k = c0 + kk;
-      s16x8 v = s16x8{0, 0, 0, 0, 0, 0, 0, 0};
-      if (k < K) {
-        const s16x8* srcp = nullptr;
-        if (PHASE == 1) {
-          if (k < u.nin) srcp = reinterpret_cast<const s16x8*>(Xs + (((int64_t)p * a.n + u.in0 + k) * kNR + 8 * ch));
-        } else {
-          const int s = a.src[u.in0 + k];
-          if (s >= 0)
-            srcp = reinterpret_cast<const s16x8*>(Xs + (((int64_t)p * a.n + a.invperm[s]) * kNR + 8 * ch));
-          else if (s < -1)
-            srcp = reinterpret_cast<const s16x8*>(Ts + (((int64_t)p * a.t_size + (-s - 1)) * kNR + 8 * ch));
-        }
-        if (srcp) v = *srcp;
-      }
-#pragma unroll
-      for (int j = 0; j < 8; ++j) zs[p][8 * ch + j][zcol(8 * ch + j, kk)] = (unsigned short)v[j];
+  for (int r = 0; r < rounds; ++r) {
+    const bool more = r + 1 < rounds;
+    if (more) {
+      stage_load<NS, PHASE>(a, u, (r + 1) * kKS, K, tid, sr);
+      if (work) load_a(pool, u, (r + 1) * kKS, o, orow, lk, an);
     }
-    __syncthreads();
+    if (work) {
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const int mt = wave + kWaves * t;
-      if (mt >= ntiles) break;
-      const int o = mt * 16 + lm;
-      const bool orow = o < u.nout;
-#pragma unroll 2
-      for (int ks = 0; ks < kKS; ks += 32) {
-        // A fragment: output o, inputs c0 + ks + 8 lk + [0, 8): two panel quads
-        const int q = (c0 + ks) / 4 + 2 * lk;
-        float av[8];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          f32x4 v = f32x4{0.f, 0.f, 0.f, 0.f};
-          if (orow && q + h < u.nq) v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(
-                                        pool + u.off + ((size_t)(q + h) * u.nout + o) * 4));
-          av[4 * h + 0] = v[0];
-          av[4 * h + 1] = v[1];
-          av[4 * h + 2] = v[2];
-          av[4 * h + 3] = v[3];
-        }
+      for (int st = 0; st < kKS / 32; ++st) {
+        // A fragment: output o, inputs 32 st + 8 lk + [0, 8) of the round
         bf16x8 ap[NS];
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           __bf16 pp[NS];
-          split<NS>(av[j], pp);
+          split<NS>(ar[st][j >> 2][j & 3], pp);
 #pragma unroll
           for (int i = 0; i < NS; ++i) ap[i][j] = pp[i];
         }
@@ -141,42 +213,48 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
         for (int nt = 0; nt < 4; ++nt) {
           bf16x8 bp[NS];
 #pragma unroll
-          for (int i = 0; i < NS; ++i)
-            bp[i] = __builtin_bit_cast(
-                bf16x8, *reinterpret_cast<const s16x8*>(&zs[i][nt * 16 + lm][zcol(nt * 16 + lm, ks + 8 * lk)]));
+          for (int i = 0; i < NS; ++i) bp[i] = __builtin_bit_cast(bf16x8, b_fragment(zs[i], 32 * st, nt * 16, lane));
 #pragma unroll
           for (int i = 0; i < NS; ++i)
 #pragma unroll
             for (int j = 0; j < NS - i; ++j)
-              acc[t][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[i], bp[j], acc[t][nt], 0, 0, 0);
+              acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[i], bp[j], acc[nt], 0, 0, 0);
         }
+        // keep the scheduler from hoisting the LDS reads of later steps
+        // (their fragments would all be live at once)
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     __syncthreads();
+    if (more) {
+      stage_store<NS>(zs, tid, sr);
+#pragma unroll
+      for (int st = 0; st < kKS / 32; ++st) {
+        ar[st][0] = an[st][0];
+        ar[st][1] = an[st][1];
+      }
+      __syncthreads();
+    }
   }
-  // write: lane holds rows mt*16 + 4 lk + [0,4), member nt*16 + lm
+  if (!work) return;
+  // write: lane holds outputs ob + 16 wave + 4 lk + [0, 4), member 16 nt + lm
 #pragma unroll
-  for (int t = 0; t < MT; ++t) {
-    const int mt = wave + kWaves * t;
-    if (mt >= ntiles) break;
+  for (int nt = 0; nt < 4; ++nt) {
+    const int r = nt * 16 + lm;
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-      const int r = nt * 16 + lm;
+    for (int i = 0; i < 4; ++i) {
+      const int oo = ob + wave * 16 + 4 * lk + i;
+      if (oo >= u.nout) continue;
+      const float v = acc[nt][i];
+      if (PHASE == 1) {
+        __bf16 pp[NS];
+        split<NS>(v, pp);
+        const int64_t slot = (int64_t)u.out0 + oo;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int o = mt * 16 + 4 * lk + i;
-        if (o >= u.nout) continue;
-        const float v = acc[t][nt][i];
-        if (PHASE == 1) {
-          __bf16 pp[NS];
-          split<NS>(v, pp);
-          const int64_t slot = (int64_t)u.out0 + o;
-#pragma unroll
-          for (int p = 0; p < NS; ++p) Ts[((int64_t)p * a.t_size + slot) * kNR + r] = pp[p];
-        } else if (r < a.nrhs) {
-          double* yp = a.Y + (int64_t)a.perm[u.out0 + o] * a.ldy + r;
-          *yp = beta == 0.0 ? alpha * (double)v : fma(alpha, (double)v, beta * *yp);
-        }
+        for (int p = 0; p < NS; ++p) Ts[((int64_t)p * a.t_size + slot) * kNR + r] = pp[p];
+      } else if (r < a.nrhs) {
+        double* yp = a.Y + (int64_t)a.perm[u.out0 + oo] * a.ldy + r;
+        *yp = beta == 0.0 ? alpha * (double)v : fma(alpha, (double)v, beta * *yp);
       }
     }
   }
@@ -188,9 +266,9 @@ hipError_t launch_ns(const MMArgs& a, double alpha, double beta, hipStream_t s, 
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_split_members<NS>), dim3((unsigned)((n * kNR + 255) / 256)), dim3(256), 0, s, n, a.nrhs, a.X,
                      a.ldx, a.perm, static_cast<__bf16*>(a.Xs));
-  if (a.n1 > 0) hipLaunchKernelGGL((k_mm<NS, 1, 4>), dim3(a.n1), dim3(kWaves * 64), 0, s, a, alpha, beta);
+  if (a.ns1 > 0) hipLaunchKernelGGL((k_mm<NS, 1>), dim3(a.ns1), dim3(kWaves * 64), 0, s, a, alpha, beta);
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (a.n2 > 0) hipLaunchKernelGGL((k_mm<NS, 2, 1>), dim3(a.n2), dim3(kWaves * 64), 0, s, a, alpha, beta);
+  if (a.n2 > 0) hipLaunchKernelGGL((k_mm<NS, 2>), dim3(a.n2), dim3(kWaves * 64), 0, s, a, alpha, beta);
   if (ev) (void)hipEventRecord(ev[2], s);
   return hipGetLastError();
 }
