@@ -191,7 +191,7 @@ def ensemble(torch, hm, workloads, reps=20):
         f = config_fault(name)
         opts = bench_options(name, "batched_f32") if name in ("dip30_480x256",) else dict(
             aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"], prec="f32",
-            kernel="split", wg_waves=8, wg_waves_p1=4)
+            kernel="split")
         H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, max_nrhs=64, **opts)
         info = H.info()
         X = torch.tensor(loguniform_rates(f.n, 3, nrhs=64), device=dev)

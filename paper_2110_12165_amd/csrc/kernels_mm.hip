@@ -167,8 +167,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
   int ui, ob = 0;
   if (PHASE == 1) {
     const int code = a.slices1[blockIdx.x];
-    ui = code >> 2;
-    ob = 64 * (code & 3);
+    ui = code >> 4;
+    ob = 64 * (code & 15);
   } else {
     ui = a.n1 + blockIdx.x;
   }

@@ -8,9 +8,9 @@
 namespace hm {
 
 struct MMArgs {
-  const Unit* units;       // batched units (phase 1 then phase 2); every nout <= 256
+  const Unit* units;       // batched units (phase 1 then phase 2); every nout <= 1024
   int32_t n1, n2;
-  const int32_t* slices1;  // 64-output slices of the phase-1 units: 4 * unit + slice
+  const int32_t* slices1;  // 64-output slices of the phase-1 units: 16 * unit + slice
   int32_t ns1;             // number of slices
   const int32_t* src;      // phase-2 input sources (user index of x, or -t-1)
   const void* pool;        // FP32 panels
