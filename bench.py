@@ -236,6 +236,73 @@ def ensemble(torch, hm, workloads, reps=20):
     return out
 
 
+def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4):
+    """64 rate-and-state simulations on the N = 21000 mesh advanced together
+    (rs_ens_rk45_run: per-member FP64 state and step control, one BF16x3 MFMA
+    ensemble product per stage), against single simulations with the FP32
+    single-vector product (rs_rk45_run), n_single of them timed and the time
+    scaled to all members."""
+    from synth import WORKLOADS, config_fault, ensemble_params
+    from synth.faults import MU, NU
+
+    name = "dip30_150x140"
+    w = WORKLOADS[name]
+    f = config_fault(name)
+    n = f.n
+    dev = torch.device("cuda:0")
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
+                         lattice=w["lattice"], prec="f32", kernel="split", max_nrhs=64)
+    p = ensemble_params(f, members, 3)
+    V = 10.0 ** (-12.0 + 3.0 * np.random.default_rng(5).random((n, members)))
+    phi = p["f0"] + p["b"] * np.log(p["V0"] / V)
+    tau = p["a"] * p["sigma"][:, None] * np.arcsinh(V / (2 * p["V0"]) * np.exp(phi / p["a"]))
+    phi = phi + np.random.default_rng(105).uniform(-0.05, 0.05, (n, members))
+    y0 = np.stack([phi, tau, np.repeat(p["sigma"][:, None], members, 1)])
+    a, b, dc = (torch.tensor(np.ascontiguousarray(p[k]), device=dev) for k in ("a", "b", "dc"))
+    consts = (p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    s = torch.cuda.Stream()
+    ens = hm.EnsembleRK45(H, None, a, b, dc, *consts, mode=mode)
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros((n, members), dtype=torch.float64, device=dev)
+    with torch.cuda.stream(s):
+        ens.run(y, D, 2, use_graph=True, stream=s)
+        s.synchronize()
+        acc0, rej0 = ens.accepted.copy(), ens.rejected.copy()
+        t0 = time.perf_counter()
+        ens.run(y, D, n_steps, use_graph=True, stream=s)
+        s.synchronize()
+        wall = time.perf_counter() - t0
+    attempts = int(np.max((ens.accepted - acc0) + (ens.rejected - rej0)))
+    # single simulations of the first n_single members, same steps
+    single = 0.0
+    single_attempts = 0
+    for r in range(n_single):
+        ar, br, dcr = (t[:, r].contiguous() for t in (a, b, dc))
+        rk = hm.RK45(H, None, ar, br, dcr, *consts)
+        yr = torch.tensor(np.ascontiguousarray(y0[:, :, r].reshape(-1)), device=dev)
+        Dr = torch.zeros(n, dtype=torch.float64, device=dev)
+        with torch.cuda.stream(s):
+            rk.run(yr, Dr, 2, use_graph=True, stream=s)
+            s.synchronize()
+            a0 = rk.state.accepted + rk.state.rejected
+            t1 = time.perf_counter()
+            rk.run(yr, Dr, n_steps, use_graph=True, stream=s)
+            s.synchronize()
+            single += time.perf_counter() - t1
+        single_attempts += rk.state.accepted + rk.state.rejected - a0
+    single_all = single / n_single * members
+    H.close()
+    torch.cuda.empty_cache()
+    log(f"[bench] ensemble rk45: {members} members x {n_steps} steps in {wall:.3f} s ({attempts} attempts); "
+        f"single simulations {single / n_single:.3f} s each -> {single_all:.3f} s for {members} (x{single_all / wall:.1f})")
+    return {"workload": name, "N": n, "members": members, "mode": mode, "steps_per_member": n_steps,
+            "attempts": attempts, "wall_s": wall, "member_steps_per_s": members * n_steps / wall,
+            "single_wall_s_each": single / n_single, "single_attempts_mean": single_attempts / n_single,
+            "speedup_vs_single_runs": single_all / wall,
+            "note": "per-element a - b ~ U[-0.006, 0.004] (b = 0.015), d_c log-uniform [0.005, 0.05] m (seed 3); "
+                    "graph-replayed attempts; single runs use the FP32 single-vector product"}
+
+
 def adjoint_run(torch, hm, n_steps, ckpt_every=50):
     """Gradient of the final-slip misfit L = 1/2 |D_M - D_target|^2 for
     per-element a (b fixed) and d_c on the N = 21000 mesh with FP32 factors:
@@ -334,6 +401,8 @@ def main():
                     help="accepted RK45 steps of the rate-and-state simulation on the same fault (0: skip)")
     ap.add_argument("--ensemble", default="dip30_150x140,dip30_480x256",
                     help="workloads of the 64-member MFMA ensemble product ('' to skip)")
+    ap.add_argument("--ens-rk-steps", type=int, default=100,
+                    help="steps per member of the ensemble integration (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
                     help="steps of the adjoint section (0: skip)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -450,6 +519,8 @@ def main():
         line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
     if args.ensemble:
         line["ensemble"] = ensemble(torch, hm, args.ensemble.split(","))
+    if args.ens_rk_steps > 0:
+        line["ensemble_rk45"] = ensemble_rk(torch, hm, args.ens_rk_steps)
     if args.adjoint_steps > 0:
         line["adjoint"] = adjoint_run(torch, hm, args.adjoint_steps)
     if not args.no_cpu_baseline:

@@ -396,6 +396,58 @@ hmat_status rs_rk45_adjoint(hmat_t A, hmat_t B, const rs_params* p, const double
                             const double* dts, int64_t n_steps, const double* D_bar, double* y_bar, double* a_bar,
                             double* dc_bar, void* workspace, int64_t workspace_bytes, void* stream);
 
+/* Ensemble of up to 64 rate-and-state simulations on one fault (section
+ * 2.2 for each member), advanced together: every member has its own
+ * friction parameters, state, slip, step and step control; at each
+ * Runge-Kutta stage the slip rates of all members go through one ensemble
+ * product (hmat_matmat's MFMA kernels).  Layout, member-fastest:
+ * element i, member r at [i * members + r]; state components (phi | tau |
+ * sigma) in three such blocks of n * members. */
+typedef struct {
+  int64_t n;               /* elements; must equal the order of A (and B) */
+  int32_t members;         /* 1..64 */
+  int32_t mode;            /* HMAT_MM_BF16X3 or HMAT_MM_BF16X6 */
+  double V0, f0, eta_rad, V_pl;   /* as in rs_params, shared by the members */
+  const double* a;         /* DEVICE n * members */
+  const double* b;         /* DEVICE n * members */
+  const double* dc;        /* DEVICE n * members */
+} rs_ens_params;
+
+/* Host state of an ensemble integration (per member). */
+typedef struct {
+  double eps_rk;           /* allowance eps_RK; <= 0 means 1e-4 */
+  double t[64];            /* simulated time of each member [s] */
+  double dt[64];           /* step each member tries next [s] (> 0) */
+  double last_err[64];     /* err / eps_RK of the member's last attempt */
+  int64_t accepted[64];
+  int64_t rejected[64];
+} rs_ens_state;
+
+/* Bytes of device workspace rs_ens_rk45_run needs: 8 * 28 * n * members plus
+ * the device state (about 5 KB); -1 on bad arguments. */
+int64_t rs_ens_workspace_bytes(int64_t n, int32_t members);
+
+/*
+ * rs_ens_rk45_run — advance every member until it has n_accept more
+ * accepted steps (members that reach it stop changing while the others
+ * continue).  Each attempt: six stages of per-member stage combinations,
+ * slip rates (eq. (7)), one ensemble product with A (and B) for all members,
+ * per-member right-hand sides (eqs. (8), (12), (13)); then per-member error
+ * (largest relative difference of the 5th- and 4th-order solutions) and
+ * step control (eqs. (14)-(15)); accepted members advance y and D (eq. (16)).
+ * The controllers run on the GPU; the host reads the state once per batch.
+ *   A: built with max_nrhs >= members (FP32 storage, a BATCHED kernel).
+ *   y: DEVICE 3 * n * members; D: DEVICE n * members; updated in place.
+ *   workspace: DEVICE, rs_ens_workspace_bytes(n, members), 8-byte aligned.
+ *   use_graph != 0 and a non-null stream: one attempt is captured as a HIP
+ *     graph (cached in A) and replayed.
+ *   max_attempts > 0 bounds the attempts (HMAT_ESTATE if a member misses
+ *     its target).  st is updated on return.
+ */
+hmat_status rs_ens_rk45_run(hmat_t A, hmat_t B, const rs_ens_params* p, double* y, double* D, void* workspace,
+                            rs_ens_state* st, int64_t n_accept, int64_t max_attempts, int32_t use_graph,
+                            void* stream);
+
 /* Release the handle and all its device memory (NULL is ignored).
  * Synchronises the device first. */
 void hmat_destroy(hmat_t h);

@@ -344,3 +344,62 @@ class RK45:
     @dt.setter
     def dt(self, v):
         self.state.dt = v
+
+
+class EnsembleRK45:
+    """Up to 64 rate-and-state simulations on one fault advanced together
+    (rs_ens_rk45_run): per-member FP64 state, parameters and step control on
+    the GPU, one MFMA ensemble product with A (and B) per stage for all
+    members.  a, b, dc: float64 GPU tensors (n, members); states y (3, n,
+    members) and slip D (n, members), contiguous."""
+
+    def __init__(self, A, B, a, b, dc, V0, f0, eta_rad, V_pl, mode="x3", eps_rk=1e-4, dt0=1.0):
+        torch = _torch()
+        n = A.n
+        if a.dim() != 2 or a.shape[0] != n or not 1 <= a.shape[1] <= 64:
+            raise ValueError("a must be (n, members) with 1 <= members <= 64")
+        m = a.shape[1]
+        for t in (a, b, dc):
+            if t.shape != (n, m) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+                raise ValueError("a, b, dc must be contiguous float64 GPU tensors of shape (n, members)")
+        self.A, self.B, self.members = A, B, m
+        self._keep = (a, b, dc)
+        self.params = _lib.RsEnsParams(n, m, _lib.MM_MODE[mode], V0, f0, eta_rad, V_pl, a.data_ptr(),
+                                       b.data_ptr(), dc.data_ptr())
+        nbytes = _lib.load().rs_ens_workspace_bytes(n, m)
+        if nbytes < 0:
+            raise ValueError("bad ensemble size")
+        self.workspace = torch.empty((nbytes + 7) // 8, dtype=torch.float64, device=a.device)
+        self.state = _lib.RsEnsState()
+        self.state.eps_rk = eps_rk
+        for r in range(64):
+            self.state.dt[r] = dt0
+
+    def run(self, y, D, n_accept, max_attempts=0, use_graph=True, stream=None):
+        """Advance every member by n_accept accepted steps (graph replay needs
+        a non-default stream)."""
+        torch = _torch()
+        n, m = self.A.n, self.members
+        if y.shape != (3, n, m) or D.shape != (n, m) or y.dtype != torch.float64 or D.dtype != torch.float64:
+            raise ValueError("y must be (3, n, members) and D (n, members) float64 GPU tensors")
+        if not (y.is_contiguous() and D.is_contiguous()):
+            raise ValueError("y and D must be contiguous")
+        check(_lib.load().rs_ens_rk45_run(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
+                                          _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), n_accept,
+                                          max_attempts, 1 if use_graph else 0, _stream_ptr(stream)))
+
+    @property
+    def t(self):
+        return np.array(self.state.t[:self.members])
+
+    @property
+    def dt(self):
+        return np.array(self.state.dt[:self.members])
+
+    @property
+    def accepted(self):
+        return np.array(self.state.accepted[:self.members])
+
+    @property
+    def rejected(self):
+        return np.array(self.state.rejected[:self.members])

@@ -62,6 +62,17 @@ class RsRk45State(C.Structure):
                 ("accepted", C.c_int64), ("rejected", C.c_int64)]
 
 
+class RsEnsParams(C.Structure):
+    _fields_ = [("n", C.c_int64), ("members", C.c_int32), ("mode", C.c_int32), ("V0", C.c_double),
+                ("f0", C.c_double), ("eta_rad", C.c_double), ("V_pl", C.c_double), ("a", C.c_void_p),
+                ("b", C.c_void_p), ("dc", C.c_void_p)]
+
+
+class RsEnsState(C.Structure):
+    _fields_ = [("eps_rk", C.c_double), ("t", C.c_double * 64), ("dt", C.c_double * 64),
+                ("last_err", C.c_double * 64), ("accepted", C.c_int64 * 64), ("rejected", C.c_int64 * 64)]
+
+
 # Symbols declared in include/hmat.h, with their ctypes signatures.
 SIGNATURES = {
     "hmat_default_opts": (None, [C.POINTER(HmatOpts)]),
@@ -95,6 +106,9 @@ SIGNATURES = {
                                   C.c_void_p, C.c_int64, C.c_void_p]),
     "rs_rk45_step": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.POINTER(RsRk45State), C.c_int32, C.c_void_p]),
+    "rs_ens_workspace_bytes": (C.c_int64, [C.c_int64, C.c_int32]),
+    "rs_ens_rk45_run": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsEnsParams), C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.POINTER(RsEnsState), C.c_int64, C.c_int64, C.c_int32, C.c_void_p]),
     "hmat_destroy": (None, [C.c_void_p]),
     "hmat_last_error": (C.c_char_p, []),
 }

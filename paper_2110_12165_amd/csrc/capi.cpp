@@ -17,6 +17,7 @@
 #include "layout.hpp"
 #include "rs.hpp"
 #include "rs_adjoint.hpp"
+#include "rs_ens.hpp"
 
 namespace {
 
@@ -62,6 +63,46 @@ hmat_status guarded(F&& f) {
 
 }  // namespace
 
+// One captured stream sequence, replayed while its key (the pointers and
+// constants it was captured with) stays the same.
+struct GraphCache {
+  hipGraph_t g = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<const void*> key;
+
+  template <typename F>
+  void ensure(const std::vector<const void*>& k, hipStream_t s, F&& enqueue) {
+    if (exec && k == key) return;
+    drop();
+    check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    try {
+      enqueue(s);
+    } catch (...) {
+      hipGraph_t tmp = nullptr;
+      (void)hipStreamEndCapture(s, &tmp);
+      if (tmp) (void)hipGraphDestroy(tmp);
+      throw;
+    }
+    check_hip(hipStreamEndCapture(s, &g), "hipStreamEndCapture");
+    check_hip(hipGraphInstantiate(&exec, g, nullptr, nullptr, 0), "hipGraphInstantiate");
+    key = k;
+  }
+
+  void drop() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (g) (void)hipGraphDestroy(g);
+    exec = nullptr;
+    g = nullptr;
+    key.clear();
+  }
+};
+
+void push_double(std::vector<const void*>& key, double c) {
+  const void* v;
+  std::memcpy(&v, &c, sizeof(v));
+  key.push_back(v);
+}
+
 struct hmat_s {
   int device = 0;
   bool on_device = false;  // false: host blocks only (hmat_build_host)
@@ -90,43 +131,13 @@ struct hmat_s {
   double* rs_ax = nullptr;  // n doubles: A (V - V_pl)
   double* rs_bx = nullptr;  // n doubles: B (V - V_pl)
   hmat_stats st{};
-  // captured Runge-Kutta attempt (rs_rk45_run), keyed by everything it reads
-  hipGraph_t rk_graph_g = nullptr;
-  hipGraphExec_t rk_exec = nullptr;
-  std::vector<const void*> rk_key;
-
-  template <typename F>
-  void rk_graph(hmat_t B, const rs_params* p, const double* y, const double* D, const void* ws, const double* dt_log,
-                hipStream_t s, F&& enqueue) {
-    std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, ws, dt_log, s};
-    const double consts[4] = {p->V0, p->f0, p->eta_rad, p->V_pl};
-    for (double c : consts) {
-      const void* v;
-      std::memcpy(&v, &c, sizeof(v));
-      key.push_back(v);
-    }
-    if (rk_exec && key == rk_key) return;
-    drop_graph();
-    check_hip(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    try {
-      enqueue(s);
-    } catch (...) {
-      hipGraph_t g = nullptr;
-      (void)hipStreamEndCapture(s, &g);
-      if (g) (void)hipGraphDestroy(g);
-      throw;
-    }
-    check_hip(hipStreamEndCapture(s, &rk_graph_g), "hipStreamEndCapture");
-    check_hip(hipGraphInstantiate(&rk_exec, rk_graph_g, nullptr, nullptr, 0), "hipGraphInstantiate");
-    rk_key = key;
-  }
+  // captured Runge-Kutta attempts (rs_rk45_run, rs_ens_rk45_run), each keyed
+  // by everything it reads
+  GraphCache rk_cache, ens_cache;
 
   void drop_graph() {
-    if (rk_exec) (void)hipGraphExecDestroy(rk_exec);
-    if (rk_graph_g) (void)hipGraphDestroy(rk_graph_g);
-    rk_exec = nullptr;
-    rk_graph_g = nullptr;
-    rk_key.clear();
+    rk_cache.drop();
+    ens_cache.drop();
   }
 
   ~hmat_s() {
@@ -527,6 +538,35 @@ hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, in
   });
 }
 
+namespace {
+
+// Ensemble product of up to 64 right-hand sides (X, Y element-major).
+void enqueue_mm(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, int32_t nrhs, double alpha,
+                double beta, int32_t mode, hipStream_t s) {
+  hm::MMArgs a{};
+  a.units = h->batched.units;
+  a.n1 = h->batched.n1;
+  a.n2 = h->batched.n2;
+  a.slices1 = h->mm_slices1;
+  a.ns1 = h->mm_ns1;
+  a.src = h->batched.src;
+  a.pool = h->batched.pool;
+  a.perm = h->d_perm;
+  a.invperm = h->d_invperm;
+  a.n = h->H.n;
+  a.t_size = h->t_size;
+  a.Xs = h->mm_xs;
+  a.Ts = h->mm_ts;
+  a.X = X;
+  a.ldx = ldx;
+  a.Y = Y;
+  a.ldy = ldy;
+  a.nrhs = nrhs;
+  check_hip(hm::launch_mm(a, mode, alpha, beta, s), "ensemble launch");
+}
+
+}  // namespace
+
 hmat_status hmat_matmat(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrhs, double alpha,
                         double beta, int32_t mode, void* stream) {
   return guarded([&] {
@@ -545,28 +585,8 @@ hmat_status hmat_matmat(hmat_t h, const double* X, int64_t ldx, double* Y, int64
     if (xa < ya + sy && ya < xa + sx) hm::fail(HMAT_EINVAL, "X and Y must not overlap");
     DeviceGuard g(h->device);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int64_t c0 = 0; c0 < nrhs; c0 += 64) {
-      hm::MMArgs a{};
-      a.units = h->batched.units;
-      a.n1 = h->batched.n1;
-      a.n2 = h->batched.n2;
-      a.slices1 = h->mm_slices1;
-      a.ns1 = h->mm_ns1;
-      a.src = h->batched.src;
-      a.pool = h->batched.pool;
-      a.perm = h->d_perm;
-      a.invperm = h->d_invperm;
-      a.n = n;
-      a.t_size = h->t_size;
-      a.Xs = h->mm_xs;
-      a.Ts = h->mm_ts;
-      a.X = X + c0;
-      a.ldx = ldx;
-      a.Y = Y + c0;
-      a.ldy = ldy;
-      a.nrhs = (int32_t)std::min<int64_t>(64, nrhs - c0);
-      check_hip(hm::launch_mm(a, mode, alpha, beta, s), "ensemble launch");
-    }
+    for (int64_t c0 = 0; c0 < nrhs; c0 += 64)
+      enqueue_mm(h, X + c0, ldx, Y + c0, ldy, (int32_t)std::min<int64_t>(64, nrhs - c0), alpha, beta, mode, s);
   });
 }
 
@@ -825,16 +845,18 @@ hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, doubl
     const long long target = st->accepted + n_accept;
     put_state(w, st, target, -1, s);
     const bool graph = use_graph && s != nullptr;
-    if (graph)
-      A->rk_graph(B, p, y, D, workspace, dt_log, s,
-                  [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, dt_log, cs); });
+    if (graph) {
+      std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, workspace, dt_log, s};
+      for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
+      A->rk_cache.ensure(key, s, [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, dt_log, cs); });
+    }
     int64_t launched = 0;
     for (;;) {
       int64_t batch = target - st->accepted;
       if (max_attempts > 0) batch = std::min(batch, max_attempts - launched);
       if (batch <= 0) break;
       for (int64_t k = 0; k < batch; ++k) {
-        if (graph) check_hip(hipGraphLaunch(A->rk_exec, s), "hipGraphLaunch");
+        if (graph) check_hip(hipGraphLaunch(A->rk_cache.exec, s), "hipGraphLaunch");
         else enqueue_attempt(A, B, p, y, D, w, dt_log, s);
       }
       launched += batch;
@@ -986,6 +1008,133 @@ hmat_status rs_rk45_adjoint(hmat_t A, hmat_t B, const rs_params* p, const double
                     "slip-term launch");
       }
     }
+  });
+}
+
+int64_t rs_ens_workspace_bytes(int64_t n, int32_t members) {
+  if (n < 0 || members < 1 || members > hm::kEnsMax) return -1;
+  return 8 * 28 * n * members + (int64_t)((sizeof(hm::EnsDevState) + 255) / 256 * 256);
+}
+
+namespace {
+
+struct EnsWs {
+  double *k, *ys, *y5, *Vs, *x, *ax, *bx;
+  hm::EnsDevState* st;
+};
+
+EnsWs ens_workspace(void* workspace, int64_t n, int32_t M) {
+  EnsWs w;
+  const int64_t nm = n * M;
+  double* base = static_cast<double*>(workspace);
+  w.k = base;
+  w.ys = w.k + 18 * nm;
+  w.y5 = w.ys + 3 * nm;
+  w.Vs = w.y5 + 3 * nm;
+  w.x = w.Vs + nm;
+  w.ax = w.x + nm;
+  w.bx = w.ax + nm;
+  w.st = reinterpret_cast<hm::EnsDevState*>(w.bx + nm);
+  return w;
+}
+
+void enqueue_ens_attempt(hmat_t A, hmat_t B, const rs_ens_params* p, double* y, double* D, const EnsWs& w,
+                         hipStream_t s) {
+  const int64_t n = A->H.n, n3 = 3 * n;
+  const int M = p->members;
+  check_hip(hm::launch_ens_begin(w.st, s), "ensemble begin launch");
+  for (int stage = 0; stage < 6; ++stage) {
+    const double* yin = y;
+    if (stage > 0) {
+      check_hip(hm::launch_ens_stage(n3, M, stage, w.st, y, w.k, w.ys, s), "ensemble stage launch");
+      yin = w.ys;
+    }
+    check_hip(hm::launch_ens_slip(n, M, p->V0, p->V_pl, p->a, yin, w.x, stage == 0 ? w.Vs : nullptr, s),
+              "ensemble slip-rate launch");
+    enqueue_mm(A, w.x, M, w.ax, M, M, 1.0, 0.0, p->mode, s);
+    if (B) enqueue_mm(B, w.x, M, w.bx, M, M, 1.0, 0.0, p->mode, s);
+    check_hip(hm::launch_ens_rhs(n, M, p->V0, p->f0, p->eta_rad, p->a, p->b, p->dc, yin, w.ax, B ? w.bx : nullptr,
+                                 w.k + stage * n3 * M, s),
+              "ensemble rhs launch");
+  }
+  check_hip(hm::launch_ens_finish_control(n3, M, w.st, y, w.k, w.y5, s), "ensemble error launch");
+  check_hip(hm::launch_ens_accept(n, M, w.st, p->V0, p->a, w.y5, w.Vs, y, D, s), "ensemble accept launch");
+}
+
+}  // namespace
+
+hmat_status rs_ens_rk45_run(hmat_t A, hmat_t B, const rs_ens_params* p, double* y, double* D, void* workspace,
+                            rs_ens_state* st, int64_t n_accept, int64_t max_attempts, int32_t use_graph,
+                            void* stream) {
+  return guarded([&] {
+    if (!A || !p || !y || !D || !workspace || !st) hm::fail(HMAT_EINVAL, "null argument");
+    if (!A->on_device || (B && !B->on_device)) hm::fail(HMAT_ESTATE, "handle holds host blocks only");
+    if (B && B->device != A->device) hm::fail(HMAT_EINVAL, "A and B live on different devices");
+    if (p->n != A->H.n || (B && B->H.n != A->H.n)) hm::fail(HMAT_EINVAL, "n does not match the handles");
+    if (p->members < 1 || p->members > hm::kEnsMax) hm::fail(HMAT_EINVAL, "members must be 1..64");
+    if (p->mode != HMAT_MM_BF16X3 && p->mode != HMAT_MM_BF16X6) hm::fail(HMAT_EINVAL, "unknown mode");
+    if (!p->a || !p->b || !p->dc) hm::fail(HMAT_EINVAL, "null friction parameter array");
+    if (!(p->V0 > 0.0) || !(p->eta_rad >= 0.0) || !std::isfinite(p->f0) || !std::isfinite(p->V_pl))
+      hm::fail(HMAT_EINVAL, "bad friction constants");
+    for (hmat_t h : {A, B})
+      if (h && (!h->mm_xs || !h->mm_ts || h->opts.max_nrhs < p->members))
+        hm::fail(HMAT_ESTATE, "handle created without max_nrhs >= members");
+    for (int r = 0; r < p->members; ++r)
+      if (!(st->dt[r] > 0.0) || !std::isfinite(st->dt[r])) hm::fail(HMAT_EINVAL, "dt must be positive and finite");
+    if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
+    if (n_accept < 0 || max_attempts < 0) hm::fail(HMAT_EINVAL, "counts must be >= 0");
+    if (n_accept == 0) return;
+    DeviceGuard g(A->device);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const int M = p->members;
+    const EnsWs w = ens_workspace(workspace, A->H.n, M);
+    hm::EnsDevState d{};
+    d.eps = st->eps_rk > 0.0 ? st->eps_rk : 1e-4;
+    d.members = M;
+    for (int r = 0; r < M; ++r) {
+      d.t[r] = st->t[r];
+      d.dt[r] = st->dt[r];
+      d.accepted[r] = st->accepted[r];
+      d.rejected[r] = st->rejected[r];
+      d.target[r] = st->accepted[r] + n_accept;
+    }
+    check_hip(hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    const bool graph = use_graph && s != nullptr;
+    if (graph) {
+      std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, workspace, s};
+      for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
+      key.push_back(reinterpret_cast<const void*>((intptr_t)(M * 16 + p->mode)));
+      A->ens_cache.ensure(key, s, [&](hipStream_t cs) { enqueue_ens_attempt(A, B, p, y, D, w, cs); });
+    }
+    int64_t launched = 0;
+    for (;;) {
+      int64_t batch = 0;
+      for (int r = 0; r < M; ++r) batch = std::max<int64_t>(batch, d.target[r] - d.accepted[r]);
+      if (max_attempts > 0) batch = std::min(batch, max_attempts - launched);
+      if (batch <= 0) break;
+      for (int64_t k = 0; k < batch; ++k) {
+        if (graph) check_hip(hipGraphLaunch(A->ens_cache.exec, s), "hipGraphLaunch");
+        else enqueue_ens_attempt(A, B, p, y, D, w, s);
+      }
+      launched += batch;
+      check_hip(hipMemcpyAsync(&d, w.st, sizeof(d), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+      check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+      bool done = true;
+      for (int r = 0; r < M; ++r) done = done && d.accepted[r] >= d.target[r];
+      if (done) break;
+    }
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    bool done = true;
+    for (int r = 0; r < M; ++r) {
+      st->t[r] = d.t[r];
+      st->dt[r] = d.dt[r];
+      st->last_err[r] = d.r[r];
+      st->accepted[r] = d.accepted[r];
+      st->rejected[r] = d.rejected[r];
+      done = done && d.accepted[r] >= d.target[r];
+    }
+    if (!done) hm::fail(HMAT_ESTATE, "a member missed its target within max_attempts");
   });
 }
 

@@ -19,3 +19,20 @@ struct RkDevState {
 };
 
 }  // namespace hm
+
+namespace hm {
+
+// Device-resident state of an ensemble integration: up to 64 members, each
+// with its own step, controller decision and counters (the members share the
+// products, not the steps).
+constexpr int kEnsMax = 64;
+struct EnsDevState {
+  double t[kEnsMax], dt[kEnsMax], dt_used[kEnsMax], r[kEnsMax];
+  unsigned long long err_bits[kEnsMax];  // per-member max relative difference (bits of a double)
+  long long accepted[kEnsMax], rejected[kEnsMax], target[kEnsMax];
+  int ok[kEnsMax], halted[kEnsMax];
+  double eps;
+  int members, pad;
+};
+
+}  // namespace hm

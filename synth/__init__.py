@@ -12,5 +12,6 @@ from .faults import (  # noqa: F401
     config_fault,
     loguniform_rates,
     friction_params,
+    ensemble_params,
     WORKLOADS,
 )
