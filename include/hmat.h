@@ -76,13 +76,19 @@ typedef enum {
   /* Unbounded isotropic medium, all elements rectangles in one plane, slip
    * along a common in-plane direction (closed form; eqs. (5)-(6) with the
    * full-space kernel).  The normal-stress matrix B of such a fault is 0. */
-  HMAT_GF_FS_RECT_COPLANAR = 1
+  HMAT_GF_FS_RECT_COPLANAR = 1,
+  /* Unbounded isotropic medium, triangular elements of any orientation
+   * (nonplanar faults), slip along each element's own in-plane direction.
+   * Closed form: the stress of a triangular dislocation loop as a line
+   * integral over its three edges (Peach-Koehler), at the centroids.  B is
+   * in general nonzero. */
+  HMAT_GF_FS_TRIANGLE = 2
 } hmat_green_kind;
 
 /* Element mesh (host memory, read during hmat_build only). */
 typedef struct {
   int64_t n;               /* number of elements, >= 1 */
-  int32_t nvert;           /* vertices per element: 4 (rectangles) */
+  int32_t nvert;           /* vertices per element: 4 (rectangles) or 3 (triangles) */
   const double* verts;     /* n * nvert * 3 coordinates [m], element-major;
                               counter-clockwise seen from the +normal side */
   const double* slip_dir;  /* n * 3 unit slip directions in the element plane */
@@ -447,6 +453,16 @@ int64_t rs_ens_workspace_bytes(int64_t n, int32_t members);
 hmat_status rs_ens_rk45_run(hmat_t A, hmat_t B, const rs_ens_params* p, double* y, double* D, void* workspace,
                             rs_ens_state* st, int64_t n_accept, int64_t max_attempts, int32_t use_graph,
                             void* stream);
+
+/*
+ * hmat_kernel_entries — evaluate kernel entries on the host, without building
+ * an H-matrix: out[k] = A[rows[k], cols[k]] (green->component 0) or B
+ * (component 1), from the same closed forms hmat_build uses (eqs. (5)-(6)).
+ * The mesh is validated as in hmat_build.  rows, cols, out: HOST, count
+ * entries; indices in [0, mesh->n).  No GPU work.
+ */
+hmat_status hmat_kernel_entries(const hmat_mesh* mesh, const hmat_green* green, int64_t count, const int64_t* rows,
+                                const int64_t* cols, double* out);
 
 /* Release the handle and all its device memory (NULL is ignored).
  * Synchronises the device first. */

@@ -64,7 +64,9 @@ class HMatrix:
 
     @classmethod
     def build(cls, verts, slip_dir, mu, nu, component=0, stream=None, **opts):
-        """hmat_build from element vertices (N, 4, 3) and slip directions (N, 3)."""
+        """hmat_build from element vertices (N, 4, 3) (coplanar rectangles) or
+        (N, 3, 3) (triangles, any orientation) and slip directions (N, 3).
+        component 0: shear tractions (A); 1: normal tractions (B)."""
         lib = _lib.load()
         verts = np.ascontiguousarray(verts, dtype=np.float64)
         slip_dir = np.ascontiguousarray(slip_dir, dtype=np.float64)
@@ -73,7 +75,8 @@ class HMatrix:
         mesh = _lib.HmatMesh(verts.shape[0], verts.shape[1],
                              verts.ctypes.data_as(C.POINTER(C.c_double)),
                              slip_dir.ctypes.data_as(C.POINTER(C.c_double)))
-        green = _lib.HmatGreen(_lib.GF_FS_RECT_COPLANAR, component, mu, nu)
+        kind = _lib.GF_FS_TRIANGLE if verts.shape[1] == 3 else _lib.GF_FS_RECT_COPLANAR
+        green = _lib.HmatGreen(kind, component, mu, nu)
         o = cls._opts(**opts)
         h = C.c_void_p()
         check(lib.hmat_build(C.byref(mesh), C.byref(green), C.byref(o), _stream_ptr(stream), C.byref(h)))
@@ -403,3 +406,25 @@ class EnsembleRK45:
     @property
     def rejected(self):
         return np.array(self.state.rejected[:self.members])
+
+
+def kernel_entries(verts, slip_dir, mu, nu, rows, cols, component=0):
+    """Kernel entries A[rows[k], cols[k]] (component 0) or B (component 1),
+    evaluated on the host by the library's closed forms (hmat_kernel_entries)."""
+    lib = _lib.load()
+    verts = np.ascontiguousarray(verts, dtype=np.float64)
+    slip_dir = np.ascontiguousarray(slip_dir, dtype=np.float64)
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    if rows.shape != cols.shape or rows.ndim != 1:
+        raise ValueError("rows and cols must be 1-D arrays of equal length")
+    mesh = _lib.HmatMesh(verts.shape[0], verts.shape[1], verts.ctypes.data_as(C.POINTER(C.c_double)),
+                         slip_dir.ctypes.data_as(C.POINTER(C.c_double)))
+    kind = _lib.GF_FS_TRIANGLE if verts.shape[1] == 3 else _lib.GF_FS_RECT_COPLANAR
+    green = _lib.HmatGreen(kind, component, mu, nu)
+    out = np.empty(rows.shape[0])
+    check(lib.hmat_kernel_entries(C.byref(mesh), C.byref(green), rows.shape[0],
+                                  rows.ctypes.data_as(C.POINTER(C.c_int64)),
+                                  cols.ctypes.data_as(C.POINTER(C.c_int64)),
+                                  out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out

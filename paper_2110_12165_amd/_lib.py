@@ -15,6 +15,7 @@ KERNEL = {"plain": 0, "split": 1, "persistent": 2, "auto": 3}
 KERNEL_NAME = {v: k for k, v in KERNEL.items()}
 MM_MODE = {"x3": 2, "x6": 3}
 GF_FS_RECT_COPLANAR = 1
+GF_FS_TRIANGLE = 2
 
 
 class HmatMesh(C.Structure):
@@ -109,6 +110,8 @@ SIGNATURES = {
     "rs_ens_workspace_bytes": (C.c_int64, [C.c_int64, C.c_int32]),
     "rs_ens_rk45_run": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsEnsParams), C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.POINTER(RsEnsState), C.c_int64, C.c_int64, C.c_int32, C.c_void_p]),
+    "hmat_kernel_entries": (C.c_int, [C.POINTER(HmatMesh), C.POINTER(HmatGreen), C.c_int64,
+                                      C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_double)]),
     "hmat_destroy": (None, [C.c_void_p]),
     "hmat_last_error": (C.c_char_p, []),
 }

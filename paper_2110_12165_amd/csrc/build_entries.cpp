@@ -61,14 +61,16 @@ class CoplanarRectEntries final : public EntryFn {
 }  // namespace
 
 EntryFn* make_entry_fn(const hmat_mesh& mesh, const hmat_green& green, Geometry& geo) {
-  if (green.kind != HMAT_GF_FS_RECT_COPLANAR) fail(HMAT_EUNSUPPORTED, "unknown Green's function kind");
+  if (green.kind != HMAT_GF_FS_RECT_COPLANAR && green.kind != HMAT_GF_FS_TRIANGLE)
+    fail(HMAT_EUNSUPPORTED, "unknown Green's function kind");
   if (green.component != 0 && green.component != 1) fail(HMAT_EINVAL, "component must be 0 (shear) or 1 (normal)");
   if (!(green.mu > 0.0) || !std::isfinite(green.mu)) fail(HMAT_EINVAL, "mu must be positive and finite");
   if (!(green.nu > -1.0 && green.nu < 0.5)) fail(HMAT_EINVAL, "nu must lie in (-1, 0.5)");
   if (mesh.n < 1) fail(HMAT_EINVAL, "mesh.n must be >= 1");
   if (mesh.n > (int64_t)INT32_MAX / 2) fail(HMAT_EINVAL, "mesh.n too large");
-  if (mesh.nvert != 4) fail(HMAT_EINVAL, "the coplanar rectangle kernel needs nvert = 4");
   if (!mesh.verts || !mesh.slip_dir) fail(HMAT_EINVAL, "mesh.verts and mesh.slip_dir must be non-null");
+  if (green.kind == HMAT_GF_FS_TRIANGLE) return make_triangle_entry_fn(mesh, green, geo);
+  if (mesh.nvert != 4) fail(HMAT_EINVAL, "the coplanar rectangle kernel needs nvert = 4");
 
   const int64_t n = mesh.n;
   const double* V = mesh.verts;

@@ -1138,6 +1138,21 @@ hmat_status rs_ens_rk45_run(hmat_t A, hmat_t B, const rs_ens_params* p, double* 
   });
 }
 
+hmat_status hmat_kernel_entries(const hmat_mesh* mesh, const hmat_green* green, int64_t count, const int64_t* rows,
+                                const int64_t* cols, double* out) {
+  return guarded([&] {
+    if (!mesh || !green || (count > 0 && (!rows || !cols || !out))) hm::fail(HMAT_EINVAL, "null argument");
+    if (count < 0) hm::fail(HMAT_EINVAL, "count must be >= 0");
+    hm::Geometry geo;
+    std::unique_ptr<hm::EntryFn> E(hm::make_entry_fn(*mesh, *green, geo));
+    for (int64_t k = 0; k < count; ++k) {
+      if (rows[k] < 0 || rows[k] >= mesh->n || cols[k] < 0 || cols[k] >= mesh->n)
+        hm::fail(HMAT_EINVAL, "entry index out of range");
+      out[k] = E->entry(rows[k], cols[k]);
+    }
+  });
+}
+
 void hmat_destroy(hmat_t h) { delete h; }
 
 const char* hmat_last_error(void) { return g_err.c_str(); }

@@ -36,6 +36,8 @@ struct Geometry {
 // Validates the mesh and Green's function and returns the entry function;
 // fills geo.centres.
 EntryFn* make_entry_fn(const hmat_mesh& mesh, const hmat_green& green, Geometry& geo);
+// The triangle kernel (called by make_entry_fn after the common checks).
+EntryFn* make_triangle_entry_fn(const hmat_mesh& mesh, const hmat_green& green, Geometry& geo);
 
 // ---------------------------------------------------------------------------
 // Cluster tree and block partition (section 3.1.1, eq. (17); section 3.2).

@@ -14,4 +14,8 @@ from .faults import (  # noqa: F401
     friction_params,
     ensemble_params,
     WORKLOADS,
+    TriangleFault,
+    curved_thrust_fault,
+    config_triangle_fault,
+    TRIANGLE_WORKLOADS,
 )

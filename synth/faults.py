@@ -158,3 +158,81 @@ def ensemble_params(f: PlanarRectFault, members: int, seed: int) -> dict:
     b = np.full((n, members), 0.015)
     return dict(a=b + amb, b=b, dc=dc, sigma=np.full(n, 50.0e6),
                 V0=V0, f0=F0, V_pl=V_PL, eta_rad=MU / (2.0 * CS), mu=MU, nu=NU)
+
+
+@dataclass
+class TriangleFault:
+    nx: int                      # quads along strike
+    ny: int                      # quads down dip
+    verts: np.ndarray = field(repr=False)     # (N, 3, 3), N = 2 nx ny
+    slip_dir: np.ndarray = field(repr=False)  # (N, 3) unit up-dip (thrust) directions
+    xs: np.ndarray = field(repr=False)        # (N,) along-strike coordinate of the centroid
+    ss: np.ndarray = field(repr=False)        # (N,) down-dip arc length of the centroid
+    depth: np.ndarray = field(repr=False)     # (N,) depth of the centroid (>= 0)
+
+    @property
+    def n(self) -> int:
+        return self.verts.shape[0]
+
+
+def dip_profile(s, dip0_deg=30.0, amp_deg=10.0, wavelength=20.0e3, substeps=200000):
+    """Fault trace in the (y, z) plane for a dip that varies down dip,
+    delta(s) = dip0 + amp sin(2 pi s / wavelength) (s = down-dip arc length):
+    y(s) = int_0^s cos(delta), z(s) = -int_0^s sin(delta), by the trapezoidal
+    rule on a uniform grid of `substeps` intervals over [0, max(s)] and linear
+    interpolation in between."""
+    s = np.asarray(s, dtype=np.float64)
+    smax = float(np.max(s))
+    g = np.linspace(0.0, smax, substeps + 1)
+    d = np.deg2rad(dip0_deg + amp_deg * np.sin(2.0 * np.pi * g / wavelength))
+    h = g[1] - g[0]
+    cy = np.concatenate([[0.0], np.cumsum(0.5 * h * (np.cos(d[1:]) + np.cos(d[:-1])))])
+    cz = np.concatenate([[0.0], -np.cumsum(0.5 * h * (np.sin(d[1:]) + np.sin(d[:-1])))])
+    return np.interp(s, g, cy), np.interp(s, g, cz)
+
+
+def curved_thrust_fault(nx: int, ny: int, length: float = 40.0e3, width: float = 20.0e3,
+                        dip0_deg: float = 30.0, amp_deg: float = 10.0, wavelength: float = 20.0e3) -> TriangleFault:
+    """Nonplanar thrust fault: a surface translated along strike (x) whose
+    dip varies down dip as in dip_profile, meshed by an nx x ny grid of quads
+    (uniform in x and in arc length s), each split along its (i, j) -> (i+1, j+1)
+    diagonal into triangles 2q and 2q + 1 (q = j nx + i).  Vertices are
+    counter-clockwise seen from the hanging wall (+normal, upward); slip is
+    up dip along each quad's chord (thrust)."""
+    xs = np.linspace(0.0, length, nx + 1)
+    sg = np.linspace(0.0, width, ny + 1)
+    ys, zs = dip_profile(sg, dip0_deg, amp_deg, wavelength)
+    P = lambda i, j: np.array([xs[i], ys[j], zs[j]])
+    n = 2 * nx * ny
+    verts = np.empty((n, 3, 3))
+    slip = np.empty((n, 3))
+    cx = np.empty(n)
+    cs = np.empty(n)
+    for j in range(ny):
+        chord = P(0, j + 1) - P(0, j)
+        up = -chord / np.linalg.norm(chord)
+        for i in range(nx):
+            q = j * nx + i
+            a, b, c, d = P(i, j), P(i + 1, j), P(i + 1, j + 1), P(i, j + 1)
+            verts[2 * q] = (a, b, c)
+            verts[2 * q + 1] = (a, c, d)
+            slip[2 * q] = slip[2 * q + 1] = up
+            cx[2 * q] = (xs[i] + 2.0 * xs[i + 1]) / 3.0
+            cs[2 * q] = (2.0 * sg[j] + sg[j + 1]) / 3.0
+            cx[2 * q + 1] = (2.0 * xs[i] + xs[i + 1]) / 3.0
+            cs[2 * q + 1] = (sg[j] + 2.0 * sg[j + 1]) / 3.0
+    depth = -verts[:, :, 2].mean(axis=1)
+    return TriangleFault(nx, ny, verts, slip, cx, cs, depth)
+
+
+TRIANGLE_WORKLOADS = {
+    # nonplanar thrust, 150 x 70 quads of ~267 x 286 m -> 21000 triangles
+    "thrust_150x70": dict(mesh=(150, 70), aca_eps=1e-6, leaf=32, eta=2.0, lattice=8, seed=1),
+    # small versions for the parity tests (same dip profile, coarser elements)
+    "thrust_16x12": dict(mesh=(16, 12), aca_eps=1e-8, leaf=16, eta=2.0, lattice=2, seed=21),
+    "thrust_40x24": dict(mesh=(40, 24), aca_eps=1e-7, leaf=24, eta=2.0, lattice=4, seed=22),
+}
+
+
+def config_triangle_fault(name: str) -> TriangleFault:
+    return curved_thrust_fault(*TRIANGLE_WORKLOADS[name]["mesh"])
