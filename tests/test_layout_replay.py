@@ -6,6 +6,8 @@ import subprocess
 
 import pytest
 
+from paper_2110_12165_amd.build import HOST_SOURCES
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 CSRC = os.path.join(ROOT, "paper_2110_12165_amd", "csrc")
 
@@ -14,7 +16,7 @@ CSRC = os.path.join(ROOT, "paper_2110_12165_amd", "csrc")
 def binary(tmp_path_factory):
     out = str(tmp_path_factory.mktemp("replay") / "layout_check")
     srcs = [os.path.join(ROOT, "tests", "cpp", "layout_check.cpp")] + [
-        os.path.join(CSRC, f) for f in ("build_entries.cpp", "build_tree.cpp", "build_aca.cpp", "layout.cpp")]
+        os.path.join(CSRC, f) for f in HOST_SOURCES]
     cmd = ["g++", "-O2", "-std=c++17", "-pthread", "-ffp-contract=off", "-I", os.path.join(ROOT, "include"),
            "-I", CSRC] + srcs + ["-o", out]
     subprocess.run(cmd, check=True)
