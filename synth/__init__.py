@@ -18,4 +18,5 @@ from .faults import (  # noqa: F401
     curved_thrust_fault,
     config_triangle_fault,
     TRIANGLE_WORKLOADS,
+    triangle_friction_params,
 )

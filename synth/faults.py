@@ -236,3 +236,18 @@ TRIANGLE_WORKLOADS = {
 
 def config_triangle_fault(name: str) -> TriangleFault:
     return curved_thrust_fault(*TRIANGLE_WORKLOADS[name]["mesh"])
+
+
+def triangle_friction_params(f: TriangleFault) -> dict:
+    """Friction of the nonplanar fault: as friction_params (a = 0.010;
+    b = 0.015 in the central 60 % along strike and down dip, by the
+    centroids' (x, s), else 0.005; d_c = 0.01 m), with sigma rising linearly
+    with the centroid depth from 20 MPa (shallowest) to 120 MPa (deepest)."""
+    L = f.xs.max() + f.xs.min()
+    W = f.ss.max() + f.ss.min()
+    vw = (np.abs(f.xs / L - 0.5) < 0.3) & (np.abs(f.ss / W - 0.5) < 0.3)
+    d0, d1 = f.depth.min(), f.depth.max()
+    sigma = 20.0e6 + 100.0e6 * (f.depth - d0) / (d1 - d0)
+    n = f.n
+    return dict(a=np.full(n, 0.010), b=np.where(vw, 0.015, 0.005), dc=np.full(n, 0.01), sigma=sigma, vw=vw,
+                V0=V0, f0=F0, V_pl=V_PL, eta_rad=MU / (2.0 * CS), mu=MU, nu=NU)

@@ -1,0 +1,143 @@
+"""GPU products and integration on a nonplanar (curved thrust) fault meshed
+with triangles: the shear matrix A and the normal matrix B (nonzero here).
+
+* N = 1920: GPU products (FP64 and FP32 storage, A and B) against the dense
+  product of the library's closed-form entries (all rows) and against rows
+  of the oracle's independent cubature (three rows);
+* N = 21000 (the paper-scale triangle mesh): FP32-batched against FP64-plain
+  and against exact rows evaluated one by one;
+* N = 96: forced-decision RK45 with sigma evolving through B, against the
+  oracle's integration on oracle-built dense matrices.
+
+Tolerances: H-matrix products within 10 ACA tolerances of the dense product
+(FP32 storage adds ~1e-7); oracle rows carry the cubature tolerance (1e-10);
+RK45 as in test_gpu_rs (1e-8 after the steps).
+"""
+import numpy as np
+import pytest
+
+from _util import rel, say
+from oracle import friction as fr
+from oracle import rk45
+from oracle.triangles import TriangleGeometry
+from synth import (TRIANGLE_WORKLOADS, config_triangle_fault, curved_thrust_fault, loguniform_rates,
+                   triangle_friction_params)
+from synth.faults import MU, NU
+
+pytestmark = pytest.mark.gpu
+
+
+def _build(hm, f, w, component, prec, kernel):
+    return hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=component, aca_eps=w["aca_eps"], eta=w["eta"],
+                            leaf=w["leaf"], lattice=w["lattice"], prec=prec, kernel=kernel)
+
+
+@pytest.fixture(scope="module")
+def mid():
+    import torch
+
+    import paper_2110_12165_amd as hm
+    f = config_triangle_fault("thrust_40x24")
+    n = f.n
+    rows, cols = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    D = [hm.kernel_entries(f.verts, f.slip_dir, MU, NU, rows.ravel(), cols.ravel(), c).reshape(n, n) for c in (0, 1)]
+    return torch, hm, f, D
+
+
+@pytest.mark.parametrize("component", [0, 1])
+@pytest.mark.parametrize("prec,kernel", [("f64", "split"), ("f32", "split"), ("f64", "plain")])
+def test_products_mid(mid, component, prec, kernel):
+    torch, hm, f, D = mid
+    w = TRIANGLE_WORKLOADS["thrust_40x24"]
+    say(f"[triangles] thrust_40x24 N={f.n} {'AB'[component]} {prec} {kernel}")
+    H = _build(hm, f, w, component, prec, kernel)
+    x = loguniform_rates(f.n, 22)
+    y = H.matvec(torch.tensor(x, device="cuda:0")).cpu().numpy()
+    H.close()
+    tol = 10 * w["aca_eps"] + (2e-7 if prec == "f32" else 0.0)
+    assert rel(y, D[component] @ x) <= tol
+
+
+def test_oracle_rows_mid(mid):
+    torch, hm, f, D = mid
+    g = TriangleGeometry(f.verts, f.slip_dir, MU, NU)
+    rows = np.array([3, 777, 1500])
+    A, B = g.blocks(rows, np.arange(f.n))
+    x = loguniform_rates(f.n, 22)
+    w = TRIANGLE_WORKLOADS["thrust_40x24"]
+    for component, ref in ((0, A), (1, B)):
+        H = _build(hm, f, w, component, "f64", "split")
+        y = H.matvec(torch.tensor(x, device="cuda:0")).cpu().numpy()
+        H.close()
+        scale = np.max(np.abs(D[component] @ x))
+        assert np.max(np.abs(y[rows] - ref @ x)) <= 10 * w["aca_eps"] * scale
+
+
+def test_paper_scale_triangles():
+    import torch
+
+    import paper_2110_12165_amd as hm
+    name = "thrust_150x70"
+    w = TRIANGLE_WORKLOADS[name]
+    f = config_triangle_fault(name)
+    say(f"[triangles] {name} N={f.n}: A and B, FP32 batched vs FP64 plain")
+    x = loguniform_rates(f.n, w["seed"])
+    xd = torch.tensor(x, device="cuda:0")
+    rows = np.random.default_rng(1).choice(f.n, 8, replace=False)
+    cols = np.arange(f.n)
+    for component in (0, 1):
+        H32 = _build(hm, f, w, component, "f32", "split")
+        y32 = H32.matvec(xd).cpu().numpy()
+        info = H32.info()
+        H32.close()
+        H64 = _build(hm, f, w, component, "f64", "plain")
+        y64 = H64.matvec(xd).cpu().numpy()
+        H64.close()
+        say(f"   {'AB'[component]}: {info['n_lr']} low-rank / {info['n_dense']} dense blocks, "
+            f"rel FP32 vs FP64 {rel(y32, y64):.2e}")
+        assert info["n_lr"] > 0
+        assert rel(y32, y64) <= 2e-5
+        exact = np.array([hm.kernel_entries(f.verts, f.slip_dir, MU, NU, np.full(f.n, i), cols, component) @ x
+                          for i in rows])
+        assert np.max(np.abs(y64[rows] - exact)) <= 1e-5 * np.max(np.abs(y64))
+
+
+def test_rk45_with_normal_stress_against_oracle():
+    import torch
+
+    import paper_2110_12165_amd as hm
+    f = curved_thrust_fault(8, 6)
+    n = f.n
+    g = TriangleGeometry(f.verts, f.slip_dir, MU, NU)
+    A, B = g.blocks(np.arange(n), np.arange(n))
+    p = triangle_friction_params(f)
+    V = loguniform_rates(n, 31)
+    y0 = fr.initial_state(V, p, p["sigma"])
+    y0[:n] += np.random.default_rng(131).uniform(-0.05, 0.05, n)
+    out = rk45.integrate(lambda y: fr.rhs(y, p, lambda v: A @ v, lambda v: B @ v), y0, 1.0, 25,
+                         slip_rate=lambda y: fr.slip_rate(y[:n], y[n:2 * n], y[2 * n:], p["a"], p["V0"]))
+    say(f"[triangles] rk45 N={n} with B: sigma moved by up to "
+        f"{np.max(np.abs(out['y'][2 * n:] - y0[2 * n:])):.3e} Pa")
+    assert np.max(np.abs(out["y"][2 * n:] - y0[2 * n:])) > 0.0
+    # the oracle's dense matrices as single dense blocks
+    perm = np.arange(n, dtype=np.int32)
+    desc = np.array([[0, 0, n, 0, n, 0]], dtype=np.int64)
+    dev = torch.device("cuda:0")
+    HA = hm.HMatrix.from_blocks(n, perm, desc, np.array([0]), A.T.reshape(-1).copy(), prec="f64", kernel="split")
+    HB = hm.HMatrix.from_blocks(n, perm, desc, np.array([0]), B.T.reshape(-1).copy(), prec="f64", kernel="split")
+    dp = {k: torch.tensor(p[k], device=dev) for k in ("a", "b", "dc")}
+    rk = hm.RK45(HA, HB, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(n, dtype=torch.float64, device=dev)
+    for t, dt, r, ok in out["log"]:
+        rk.dt = dt
+        rk.attempt(y, D, force=1 if ok else 0)
+    yg, Dg = y.cpu().numpy(), D.cpu().numpy()
+    for c in range(3):
+        sl = slice(c * n, (c + 1) * n)
+        ref = out["y"][sl]
+        scale = np.max(np.abs(ref - y0[sl])) if c == 2 else np.max(np.abs(ref))
+        assert np.max(np.abs(yg[sl] - ref)) <= 1e-8 * scale, c
+    assert np.max(np.abs(Dg - out["D"])) <= 1e-8 * np.max(np.abs(out["D"]))
+    HA.close()
+    HB.close()
