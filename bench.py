@@ -303,6 +303,60 @@ def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4):
                     "graph-replayed attempts; single runs use the FP32 single-vector product"}
 
 
+def nonplanar(torch, hm, reps=50):
+    """Curved thrust fault of 21000 triangles (dip 30 +/- 10 degrees down dip):
+    shear (A) and normal (B) matrices, FP32-batched against FP64-plain."""
+    from synth import TRIANGLE_WORKLOADS, config_triangle_fault, loguniform_rates
+    from synth.faults import MU, NU
+
+    name = "thrust_150x70"
+    w = TRIANGLE_WORKLOADS[name]
+    f = config_triangle_fault(name)
+    dev = torch.device("cuda:0")
+    x = torch.tensor(loguniform_rates(f.n, w["seed"]), device=dev)
+    y = torch.empty_like(x)
+    out = {"workload": name, "N": f.n}
+
+    def timed(H):
+        for _ in range(5):
+            H.matvec(x, y=y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            H.matvec(x, y=y)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    for comp, label in ((0, "A"), (1, "B")):
+        res = {}
+        ys = {}
+        for prec, kernel in (("f32", "split"), ("f64", "plain")):
+            t0 = time.perf_counter()
+            H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=comp, aca_eps=w["aca_eps"], eta=w["eta"],
+                                 leaf=w["leaf"], lattice=w["lattice"], prec=prec, kernel=kernel)
+            build = time.perf_counter() - t0
+            info = H.info()
+            ms = timed(H)
+            ys[prec] = H.matvec(x).cpu().numpy()
+            H.close()
+            res[f"{prec}_{kernel}"] = {"ms": ms, "matvec_per_s": 1e3 / ms, "build_s": build,
+                                       "factor_bytes": info["factor_bytes"],
+                                       "gbs": info["alg_bytes"] / (ms * 1e-3) / 1e9}
+        res["n_lr"], res["n_dense"] = info["n_lr"], info["n_dense"]
+        res["stored_fraction"] = (info["dense_entries"] + info["lr_entries"]) / float(f.n) ** 2
+        res["speedup_f32_batched_vs_f64_plain"] = res["f64_plain"]["ms"] / res["f32_split"]["ms"]
+        res["rel_diff_f32_vs_f64"] = float(np.linalg.norm(ys["f32"] - ys["f64"]) / np.linalg.norm(ys["f64"]))
+        out[label] = res
+        log(f"[bench] nonplanar {label}: FP32 batched {res['f32_split']['ms'] * 1e3:.1f} us, FP64 plain "
+            f"{res['f64_plain']['ms'] * 1e3:.1f} us (x{res['speedup_f32_batched_vs_f64_plain']:.1f}), "
+            f"rel {res['rel_diff_f32_vs_f64']:.1e}, stored {100 * res['stored_fraction']:.1f} % of dense, "
+            f"build {res['f32_split']['build_s']:.1f} s")
+    torch.cuda.empty_cache()
+    return out
+
+
 def adjoint_run(torch, hm, n_steps, ckpt_every=50):
     """Gradient of the final-slip misfit L = 1/2 |D_M - D_target|^2 for
     per-element a (b fixed) and d_c on the N = 21000 mesh with FP32 factors:
@@ -401,6 +455,7 @@ def main():
                     help="accepted RK45 steps of the rate-and-state simulation on the same fault (0: skip)")
     ap.add_argument("--ensemble", default="dip30_150x140,dip30_480x256",
                     help="workloads of the 64-member MFMA ensemble product ('' to skip)")
+    ap.add_argument("--no-nonplanar", action="store_true", help="skip the triangle-mesh section")
     ap.add_argument("--ens-rk-steps", type=int, default=100,
                     help="steps per member of the ensemble integration (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
@@ -519,6 +574,8 @@ def main():
         line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
     if args.ensemble:
         line["ensemble"] = ensemble(torch, hm, args.ensemble.split(","))
+    if not args.no_nonplanar:
+        line["nonplanar"] = nonplanar(torch, hm)
     if args.ens_rk_steps > 0:
         line["ensemble_rk45"] = ensemble_rk(torch, hm, args.ens_rk_steps)
     if args.adjoint_steps > 0:
