@@ -166,3 +166,39 @@ def test_import_validates_tiling(lib):
                              off.ctypes.data_as(C.POINTER(C.c_int64)),
                              vals2.ctypes.data_as(C.POINTER(C.c_double)))
     assert so.hmat_import(C.byref(hb2), C.byref(o), None, C.byref(h)) == -1
+
+
+def test_integration_entry_points_reject_bad_arguments(lib):
+    """Argument checks of the replay, adjoint and ensemble entry points run
+    before any device work (host-only handle or null pointers)."""
+    so = lib.load()
+    f = planar_rect_fault(8, 8, 100.0, 90.0, "strike")
+    st, h = _host_build(lib, f, dict(aca_eps=1e-6, eta=2.0, leaf=4, lattice=1))
+    assert st == 0
+    prm = lib.RsParams(64, 1e-6, 0.6, 4.6e6, 1e-9, 16, 16, 16)
+    dts = (C.c_double * 2)(1.0, 2.0)
+    # null parameters / handle
+    assert so.rs_rk45_replay(None, None, C.byref(prm), C.c_void_p(16), None, dts, 2, None, 1, C.c_void_p(16), None) == -1
+    assert so.rs_rk45_replay(h, None, None, C.c_void_p(16), None, dts, 2, None, 1, C.c_void_p(16), None) == -1
+    # ensemble: host-only handle, bad member counts, bad mode
+    ep = lib.RsEnsParams(64, 8, 2, 1e-6, 0.6, 4.6e6, 1e-9, 16, 16, 16)
+    es = lib.RsEnsState()
+    for r in range(64):
+        es.dt[r] = 1.0
+    assert so.rs_ens_rk45_run(h, None, C.byref(ep), C.c_void_p(16), C.c_void_p(16), C.c_void_p(16), C.byref(es),
+                              1, 0, 0, None) == -4
+    so.hmat_destroy(h)
+    assert so.rs_ens_workspace_bytes(100, 0) == -1
+    assert so.rs_ens_workspace_bytes(100, 65) == -1
+    assert so.rs_ens_workspace_bytes(-1, 8) == -1
+    assert so.rs_ens_workspace_bytes(100, 8) >= 8 * 28 * 100 * 8
+    # kernel entries: out-of-range index
+    verts = np.ascontiguousarray(f.verts)
+    sd = np.ascontiguousarray(f.slip_dir)
+    mesh = lib.HmatMesh(f.n, 4, verts.ctypes.data_as(C.POINTER(C.c_double)), sd.ctypes.data_as(C.POINTER(C.c_double)))
+    green = lib.HmatGreen(lib.GF_FS_RECT_COPLANAR, 0, 32e9, 0.25)
+    rows = (C.c_int64 * 1)(f.n)
+    cols = (C.c_int64 * 1)(0)
+    out = (C.c_double * 1)()
+    assert so.hmat_kernel_entries(C.byref(mesh), C.byref(green), 1, rows, cols, out) == -1
+    assert b"range" in so.hmat_last_error()
