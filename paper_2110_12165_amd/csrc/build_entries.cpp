@@ -35,27 +35,15 @@ inline void cross3(const double* a, const double* b, double* c) {
 
 inline double norm3(const double* a) { return std::sqrt((a[0] * a[0] + a[1] * a[1]) + a[2] * a[2]); }
 
-inline double rect_traction(double x1, double x2, double a1, double b1, double a2, double b2,
-                            double mu, double nu) {
-  const double ua = x1 - a1, ub = x1 - b1, va = x2 - a2, vb = x2 - b2;
-  auto F = [](double u, double v) { return v / (u * std::sqrt(u * u + v * v)); };
-  auto G = [](double u, double v) { return u / (v * std::sqrt(u * u + v * v)); };
-  const double j1 = -(F(ua, va) - F(ub, va) - F(ua, vb) + F(ub, vb));
-  const double j2 = -(G(ua, va) - G(ub, va) - G(ua, vb) + G(ub, vb));
-  return mu / (4.0 * M_PI) * (j1 / (1.0 - nu) + j2);
-}
-
 class CoplanarRectEntries final : public EntryFn {
  public:
   int64_t n;
   double mu, nu;
-  bool zero;  // normal component: identically 0
-  std::vector<double> p1, p2, lo1, hi1, lo2, hi2;
+  int component;              // 1: normal traction, identically 0
+  std::vector<double> a;      // p1, p2, lo1, hi1, lo2, hi2 (n each)
 
-  double entry(int64_t i, int64_t j) const override {
-    if (zero) return 0.0;
-    return rect_traction(p1[i], p2[i], lo1[j], hi1[j], lo2[j], hi2[j], mu, nu);
-  }
+  EntryView view() const override { return EntryView{HMAT_GF_FS_RECT_COPLANAR, component, mu, nu, n, a.data()}; }
+  double entry(int64_t i, int64_t j) const override { return entry_of(view(), i, j); }
 };
 
 }  // namespace
@@ -83,7 +71,7 @@ EntryFn* make_entry_fn(const hmat_mesh& mesh, const hmat_green& green, Geometry&
   E->n = n;
   E->mu = green.mu;
   E->nu = green.nu;
-  E->zero = green.component == 1;
+  E->component = green.component;
 
   // Plane and in-plane axes from element 0.
   double d1[3], d3[3], nrm[3], e1[3], e2[3];
@@ -102,8 +90,13 @@ EntryFn* make_entry_fn(const hmat_mesh& mesh, const hmat_green& green, Geometry&
 
   geo.n = n;
   geo.centres.resize(3 * n);
-  E->p1.resize(n); E->p2.resize(n);
-  E->lo1.resize(n); E->hi1.resize(n); E->lo2.resize(n); E->hi2.resize(n);
+  E->a.resize(6 * n);
+  double* p1 = E->a.data();
+  double* p2 = p1 + n;
+  double* lo1 = p2 + n;
+  double* hi1 = lo1 + n;
+  double* lo2 = hi1 + n;
+  double* hi2 = lo2 + n;
 
   // Tolerances relative to the element size scale.
   double scale = 0.0;
@@ -167,9 +160,9 @@ EntryFn* make_entry_fn(const hmat_mesh& mesh, const hmat_green& green, Geometry&
       if (!ok1 || !ok2)
         fail(HMAT_EINVAL, "element " + std::to_string(i) + ": edges must be parallel and normal to the slip direction");
     }
-    E->p1[i] = dot3(c, e1);
-    E->p2[i] = dot3(c, e2);
-    E->lo1[i] = l1; E->hi1[i] = h1; E->lo2[i] = l2; E->hi2[i] = h2;
+    p1[i] = dot3(c, e1);
+    p2[i] = dot3(c, e2);
+    lo1[i] = l1; hi1[i] = h1; lo2[i] = l2; hi2[i] = h2;
   }
   return E.release();
 }

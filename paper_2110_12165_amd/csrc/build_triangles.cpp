@@ -47,64 +47,15 @@
 namespace hm {
 namespace {
 
-struct V3 {
-  double x, y, z;
-};
-inline V3 operator-(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
-inline V3 operator+(V3 a, V3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
-inline V3 operator*(double s, V3 a) { return {s * a.x, s * a.y, s * a.z}; }
-inline double dot(V3 a, V3 b) { return (a.x * b.x + a.y * b.y) + a.z * b.z; }
-inline V3 cross(V3 a, V3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
-inline double norm(V3 a) { return std::sqrt(dot(a, a)); }
-
-// u . sigma . v at x for unit slip b on the loop verts[0] -> verts[1] -> verts[2].
-double loop_traction(V3 x, const V3* verts, V3 b, V3 u, V3 v, double mu, double nu) {
-  const double k1 = mu / (4.0 * M_PI), k2 = mu / (4.0 * M_PI * (1.0 - nu));
-  const double uv = dot(u, v);
-  double out = 0.0;
-  for (int e = 0; e < 3; ++e) {
-    const V3 A = verts[e], B = verts[(e + 1) % 3];
-    const V3 AB = B - A;
-    const double L = norm(AB);
-    const V3 t = (1.0 / L) * AB;
-    const V3 rA = x - A, rB = x - B;
-    const double zA = dot(rA, t), zB = dot(rB, t);
-    const V3 p = rA - zA * t;
-    const double rho2 = dot(p, p);
-    const double RA = norm(rA), RB = norm(rB);
-    const double cA = zA / RA, cB = zB / RB;
-    const double J30 = zA * zB > 0.0 ? (zA * zA - zB * zB) / ((zA * RB + zB * RA) * RA * RB) : (cA - cB) / rho2;
-    const double J31 = -1.0 / RA + 1.0 / RB;
-    const double K = 1.0 / (RA * RA) + 1.0 / (RB * RB) + (zA * zA + zB * zB + rho2) / ((RA * RB + zA * zB) * RA * RB);
-    const double J50 = J30 * K / 3.0;
-    const double J51 = -1.0 / (3.0 * RA * RA * RA) + 1.0 / (3.0 * RB * RB * RB);
-    const double J52 = J30 * (cA * cA + cA * cB + cB * cB) / 3.0;
-    const V3 I3 = J30 * p + J31 * t;  // int r / R^3 ds
-    const V3 dPsi = -1.0 * I3;
-    const V3 c = cross(dPsi, b);
-    const V3 beta = cross(b, t);
-    const double bp = dot(beta, p), up = dot(u, p), vp = dot(v, p), ut = dot(u, t), vt = dot(v, t);
-    const double D = 3.0 * (bp * up * vp * J50 + J51 * bp * (up * vt + ut * vp) + J52 * bp * ut * vt) -
-                     (dot(beta, u) * dot(I3, v) + dot(beta, v) * dot(I3, u) + uv * dot(beta, I3));
-    out += -k1 * (dot(c, u) * vt + dot(c, v) * ut) - k2 * (D - 2.0 * uv * dot(beta, dPsi));
-  }
-  return out;
-}
-
 class TriangleEntries final : public EntryFn {
  public:
+  int64_t n;
   double mu, nu;
-  bool normal;                          // B (normal traction) instead of A
-  std::vector<V3> verts, cen, nrm, slip;  // 3 n, n, n, n
+  int component;            // 0: A (shear), 1: B (normal)
+  std::vector<double> a;    // vertices 9n, centroids 3n, unit normals 3n, unit slips 3n
 
-  double entry(int64_t i, int64_t j) const override {
-    const V3 n = nrm[i];
-    if (normal) {
-      if (i == j) return 0.0;  // in-plane slip: no normal traction on its own plane
-      return -loop_traction(cen[i], &verts[3 * j], slip[j], n, n, mu, nu);
-    }
-    return loop_traction(cen[i], &verts[3 * j], slip[j], slip[i], n, mu, nu);
-  }
+  EntryView view() const override { return EntryView{HMAT_GF_FS_TRIANGLE, component, mu, nu, n, a.data()}; }
+  double entry(int64_t i, int64_t j) const override { return entry_of(view(), i, j); }
 };
 
 }  // namespace
@@ -118,35 +69,36 @@ EntryFn* make_triangle_entry_fn(const hmat_mesh& mesh, const hmat_green& green, 
   for (int64_t k = 0; k < n * 3; ++k)
     if (!std::isfinite(mesh.slip_dir[k])) fail(HMAT_EINVAL, "non-finite slip direction");
   auto E = std::make_unique<TriangleEntries>();
+  E->n = n;
   E->mu = green.mu;
   E->nu = green.nu;
-  E->normal = green.component == 1;
-  E->verts.resize(3 * n);
-  E->cen.resize(n);
-  E->nrm.resize(n);
-  E->slip.resize(n);
+  E->component = green.component;
+  E->a.resize(18 * n);
+  double* pv = E->a.data();
+  double* pc = pv + 9 * n;
+  double* pn = pc + 3 * n;
+  double* ps = pn + 3 * n;
   geo.n = n;
   geo.centres.resize(3 * n);
   for (int64_t i = 0; i < n; ++i) {
     const double* v = Vp + 9 * i;
     const V3 a{v[0], v[1], v[2]}, b{v[3], v[4], v[5]}, c{v[6], v[7], v[8]};
-    E->verts[3 * i] = a;
-    E->verts[3 * i + 1] = b;
-    E->verts[3 * i + 2] = c;
-    const V3 cr = cross(b - a, c - a);
-    const double area2 = norm(cr);
-    const double lmax = std::fmax(norm(b - a), std::fmax(norm(c - b), norm(a - c)));
+    for (int k = 0; k < 9; ++k) pv[9 * i + k] = v[k];
+    const V3 cr = v3cross(v3sub(b, a), v3sub(c, a));
+    const double area2 = v3norm(cr);
+    const double lmax = std::fmax(v3norm(v3sub(b, a)), std::fmax(v3norm(v3sub(c, b)), v3norm(v3sub(a, c))));
     if (!(area2 > 1e-12 * lmax * lmax)) fail(HMAT_EINVAL, "degenerate element " + std::to_string(i));
-    const V3 nn = (1.0 / area2) * cr;
+    const V3 nn = v3scale(1.0 / area2, cr);
     const V3 s{mesh.slip_dir[3 * i], mesh.slip_dir[3 * i + 1], mesh.slip_dir[3 * i + 2]};
-    const double sn = norm(s);
+    const double sn = v3norm(s);
     if (!(sn > 0.0)) fail(HMAT_EINVAL, "zero slip direction at element " + std::to_string(i));
-    if (std::fabs(dot(s, nn)) > 1e-6 * sn)
+    if (std::fabs(v3dot(s, nn)) > 1e-6 * sn)
       fail(HMAT_EINVAL, "element " + std::to_string(i) + ": slip direction not in the element plane");
-    E->nrm[i] = nn;
-    E->slip[i] = (1.0 / sn) * s;
-    const V3 ce = (1.0 / 3.0) * ((a + b) + c);
-    E->cen[i] = ce;
+    const V3 su = v3scale(1.0 / sn, s);
+    const V3 ce = v3scale(1.0 / 3.0, v3add(v3add(a, b), c));
+    pc[3 * i] = ce.x; pc[3 * i + 1] = ce.y; pc[3 * i + 2] = ce.z;
+    pn[3 * i] = nn.x; pn[3 * i + 1] = nn.y; pn[3 * i + 2] = nn.z;
+    ps[3 * i] = su.x; ps[3 * i + 1] = su.y; ps[3 * i + 2] = su.z;
     geo.centres[3 * i] = ce.x;
     geo.centres[3 * i + 1] = ce.y;
     geo.centres[3 * i + 2] = ce.z;

@@ -6,6 +6,7 @@
 #include <string>
 #include <vector>
 
+#include "entries.hpp"
 #include "hmat.h"
 
 namespace hm {
@@ -26,6 +27,9 @@ class EntryFn {
   virtual ~EntryFn() = default;
   // A(i, j) in user element order.
   virtual double entry(int64_t i, int64_t j) const = 0;
+  // The packed per-element data behind entry() (see entries.hpp), valid
+  // while this object lives; used to evaluate entries on the device.
+  virtual EntryView view() const = 0;
 };
 
 struct Geometry {
