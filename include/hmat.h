@@ -119,6 +119,9 @@ typedef struct {
                               HMAT_F32, a BATCHED kernel and wg_waves_p1 <= 4); 0: none */
   int32_t transpose;       /* 1: also lay out H^T for hmat_matvec_T (doubles the factor
                               storage); 0: hmat_matvec_T returns HMAT_ESTATE */
+  int32_t build_device;    /* hmat_build: 1 = evaluate entries and run ACA on the GPU (same
+                              rules; blocks beyond rank 64 fall back to the host); 0 = host
+                              threads.  Ignored by hmat_build_host. */
 } hmat_opts;
 
 /* Arithmetic of hmat_matmat: FP32 factors and member values are split into

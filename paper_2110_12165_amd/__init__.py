@@ -50,7 +50,7 @@ class HMatrix:
     # -- construction -------------------------------------------------------
     @staticmethod
     def _opts(aca_eps=1e-6, eta=2.0, leaf=32, lattice=1, max_rank=0, prec="f64", kernel="auto",
-              n_threads=0, wg_waves=0, unit_kib=0, wg_waves_p1=0, max_nrhs=0, transpose=1):
+              n_threads=0, wg_waves=0, unit_kib=0, wg_waves_p1=0, max_nrhs=0, transpose=1, build_device=0):
         lib = _lib.load()
         o = _lib.HmatOpts()
         lib.hmat_default_opts(C.byref(o))
@@ -60,6 +60,7 @@ class HMatrix:
         o.n_threads, o.wg_waves, o.unit_kib, o.wg_waves_p1 = n_threads, wg_waves, unit_kib, wg_waves_p1
         o.max_nrhs = max_nrhs
         o.transpose = transpose
+        o.build_device = build_device
         return o
 
     @classmethod

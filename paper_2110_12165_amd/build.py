@@ -20,7 +20,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhmat.so")
 ARCH = "gfx950"
 
-HIP_SOURCES = ["kernels.hip", "kernels_mm.hip", "rs.hip", "rs_adjoint.hip", "rs_ens.hip", "capi.cpp"]
+HIP_SOURCES = ["kernels.hip", "kernels_mm.hip", "rs.hip", "rs_adjoint.hip", "rs_ens.hip", "build_gpu.hip", "capi.cpp"]
 HOST_SOURCES = ["build_entries.cpp", "build_triangles.cpp", "build_tree.cpp", "build_aca.cpp", "layout.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -304,6 +304,7 @@ void check_opts(const hmat_opts& o, bool build) {
   if (o.unit_kib < 0) hm::fail(HMAT_EINVAL, "unit_kib must be >= 0");
   if (o.max_nrhs < 0) hm::fail(HMAT_EINVAL, "max_nrhs must be >= 0");
   if (o.transpose != 0 && o.transpose != 1) hm::fail(HMAT_EINVAL, "transpose must be 0 or 1");
+  if (o.build_device != 0 && o.build_device != 1) hm::fail(HMAT_EINVAL, "build_device must be 0 or 1");
 }
 
 // Default schedule of the batched product (fastest measured on MI355X for
@@ -452,7 +453,10 @@ hmat_status hmat_build(const hmat_mesh* mesh, const hmat_green* green, const hma
     std::unique_ptr<hm::EntryFn> E(hm::make_entry_fn(*mesh, *green, geo));
     hm::ClusterTree tree = hm::build_tree(geo, opts->leaf);
     std::vector<hm::BlockSpec> blocks = hm::partition(tree, opts->lattice, opts->eta);
-    hm::HostMatrix H = hm::assemble(*E, tree, blocks, opts->aca_eps, opts->max_rank, opts->n_threads);
+    hm::HostMatrix H =
+        opts->build_device
+            ? hm::assemble_device(*E, tree, blocks, opts->aca_eps, opts->max_rank, stream)
+            : hm::assemble(*E, tree, blocks, opts->aca_eps, opts->max_rank, opts->n_threads);
     H.lattice = opts->lattice;
     hmat_t h = create_handle(std::move(H), *opts, static_cast<hipStream_t>(stream));
     refresh_stats(h);

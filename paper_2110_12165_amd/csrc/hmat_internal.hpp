@@ -94,6 +94,13 @@ bool aca_block(const EntryFn& A, const int64_t* rows, int64_t m, const int64_t* 
 HostMatrix assemble(const EntryFn& A, const ClusterTree& tree, const std::vector<BlockSpec>& blocks,
                     double eps, int32_t max_rank, int32_t n_threads);
 
+// The same block list built on the device (build_gpu.hip): ACA of the
+// admissible blocks and entries of the dense ones on the GPU, with the rules
+// of assemble(); blocks beyond the device rank cap go through aca_block().
+// stream: a hipStream_t (or null).
+HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std::vector<BlockSpec>& blocks,
+                           double eps, int32_t max_rank, void* stream);
+
 // Checks that blocks tile the matrix once and perm is a permutation.
 void validate_host_matrix(const HostMatrix& H);
 
