@@ -357,6 +357,34 @@ def nonplanar(torch, hm, reps=50):
     return out
 
 
+def construction(torch, hm, f, opts, x):
+    """Build time of the headline matrix (FP32 batched, with the transposed
+    layout) from the element geometry: host ACA on all host threads versus
+    ACA and dense entries on the GPU.  Both include packing and upload; the
+    block lists must agree (same ranks), the products to FP32 rounding."""
+    from synth.faults import MU, NU
+    out = {}
+    ys = {}
+    for dev_build in (0, 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, build_device=dev_build, **opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        info = H.info()
+        ys[dev_build] = H.matvec(x).cpu().numpy()
+        out["device_s" if dev_build else "host_s"] = dt
+        out["n_lr_device" if dev_build else "n_lr_host"] = info["n_lr"]
+        out["sum_rank_device" if dev_build else "sum_rank_host"] = info["sum_rank"]
+        H.close()
+        torch.cuda.empty_cache()
+    out["rel_diff_products"] = float(np.linalg.norm(ys[1] - ys[0]) / np.linalg.norm(ys[0]))
+    out["host_threads"] = len(os.sched_getaffinity(0))
+    log(f"[bench] construction: host {out['host_s']:.2f} s, device {out['device_s']:.2f} s; ranks "
+        f"{out['sum_rank_host']} / {out['sum_rank_device']}; products differ by {out['rel_diff_products']:.1e}")
+    return out
+
+
 def adjoint_run(torch, hm, n_steps, ckpt_every=50):
     """Gradient of the final-slip misfit L = 1/2 |D_M - D_target|^2 for
     per-element a (b fixed) and d_c on the N = 21000 mesh with FP32 factors:
@@ -456,6 +484,7 @@ def main():
     ap.add_argument("--ensemble", default="dip30_150x140,dip30_480x256",
                     help="workloads of the 64-member MFMA ensemble product ('' to skip)")
     ap.add_argument("--no-nonplanar", action="store_true", help="skip the triangle-mesh section")
+    ap.add_argument("--no-construction", action="store_true", help="skip the host/device build timing")
     ap.add_argument("--ens-rk-steps", type=int, default=100,
                     help="steps per member of the ensemble integration (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
@@ -570,6 +599,8 @@ def main():
     if "batched_f64" in outputs:
         ref = outputs["batched_f64"]
         line["rel_diff_f32_vs_f64_gpu"] = float(np.linalg.norm(outputs["batched_f32"] - ref) / np.linalg.norm(ref))
+    if not args.no_construction:
+        line["construction"] = construction(torch, hm, f, bench_options(WORKLOAD, "batched_f32"), x)
     if args.rk_steps > 0:
         line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
     if args.ensemble:

@@ -149,7 +149,7 @@ HostMatrix assemble(const EntryFn& A, const ClusterTree& tree, const std::vector
     total += (int64_t)(res[b].a.size() + res[b].b.size());
   }
   H.values.resize(total);
-  for (int64_t b = 0; b < nb; ++b) {
+  parallel_for(nb, n_threads, [&](int64_t b) {
     const BlockSpec& s = blocks[b];
     int64_t* d = &H.desc[6 * b];
     d[0] = res[b].kind;
@@ -158,7 +158,7 @@ HostMatrix assemble(const EntryFn& A, const ClusterTree& tree, const std::vector
     std::copy(res[b].b.begin(), res[b].b.end(), H.values.begin() + H.off[b] + res[b].a.size());
     std::vector<double>().swap(res[b].a);
     std::vector<double>().swap(res[b].b);
-  }
+  });
   H.tree_depth = tree.max_depth;
   return H;
 }

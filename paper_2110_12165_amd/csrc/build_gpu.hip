@@ -20,6 +20,7 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <deque>
 #include <string>
 
 #include "hmat_internal.hpp"
@@ -289,10 +290,77 @@ void upload(DevBuf& d, const std::vector<T>& v, hipStream_t s) {
   if (!v.empty()) hip_ok(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s), "upload");
 }
 
+// Pinned host buffer released on scope exit.
+struct PinnedBuf {
+  void* p = nullptr;
+  explicit PinnedBuf(size_t bytes) { hip_ok(hipHostMalloc(&p, bytes, hipHostMallocDefault), "hipHostMalloc"); }
+  PinnedBuf(const PinnedBuf&) = delete;
+  PinnedBuf& operator=(const PinnedBuf&) = delete;
+  ~PinnedBuf() { (void)hipHostFree(p); }
+};
+
+struct Event {
+  hipEvent_t e = nullptr;
+  Event() { hip_ok(hipEventCreateWithFlags(&e, hipEventDisableTiming), "hipEventCreate"); }
+  Event(const Event&) = delete;
+  Event& operator=(const Event&) = delete;
+  ~Event() { (void)hipEventDestroy(e); }
+};
+
+// A run of `len` doubles at offset soff of a device buffer, bound for dst.
+struct Segment {
+  long long soff, len;
+  double* dst;
+};
+
+// Device-to-host copy of the segments (sorted by soff, disjoint) of the
+// buffer src through two pinned staging halves: the DMA of one chunk runs
+// while host threads scatter the previous one to the destinations.
+class Downloader {
+ public:
+  static constexpr long long kChunk = 1 << 22;  // doubles per staging half (32 MiB)
+  Downloader(hipStream_t s, int32_t n_threads) : s_(s), nt_(n_threads), stage_(2 * kChunk * sizeof(double)) {}
+
+  void run(const double* src, long long total, const std::vector<Segment>& segs) {
+    if (total <= 0 || segs.empty()) return;
+    double* stage = static_cast<double*>(stage_.p);
+    const long long nch = (total + kChunk - 1) / kChunk;
+    auto enqueue = [&](long long c) {
+      const long long a = c * kChunk, len = std::min(kChunk, total - a);
+      hip_ok(hipMemcpyAsync(stage + (c & 1) * kChunk, src + a, len * sizeof(double), hipMemcpyDeviceToHost, s_),
+             "download");
+      hip_ok(hipEventRecord(ev_[c & 1].e, s_), "hipEventRecord");
+    };
+    enqueue(0);
+    size_t first = 0;
+    for (long long c = 0; c < nch; ++c) {
+      // the other half was scattered in the previous iteration
+      if (c + 1 < nch) enqueue(c + 1);
+      hip_ok(hipEventSynchronize(ev_[c & 1].e), "download");
+      const long long a = c * kChunk, b = std::min(total, a + kChunk);
+      const double* st = stage + (c & 1) * kChunk;
+      while (first < segs.size() && segs[first].soff + segs[first].len <= a) ++first;
+      size_t last = first;
+      while (last < segs.size() && segs[last].soff < b) ++last;
+      parallel_for((int64_t)(last - first), nt_, [&](int64_t k) {
+        const Segment& g = segs[first + k];
+        const long long lo = std::max(a, g.soff), hi = std::min(b, g.soff + g.len);
+        if (hi > lo) std::memcpy(g.dst + (lo - g.soff), st + (lo - a), (hi - lo) * sizeof(double));
+      });
+    }
+  }
+
+ private:
+  hipStream_t s_;
+  int32_t nt_;
+  PinnedBuf stage_;
+  Event ev_[2];
+};
+
 }  // namespace
 
 HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std::vector<BlockSpec>& blocks,
-                           double eps, int32_t max_rank, void* stream) {
+                           double eps, int32_t max_rank, int32_t n_threads, void* stream) {
   const hipStream_t s = static_cast<hipStream_t>(stream);
   if (!(eps > 0.0) || !std::isfinite(eps)) fail(HMAT_EINVAL, "aca_eps must be positive");
   if (max_rank < 0) fail(HMAT_EINVAL, "max_rank must be >= 0");
@@ -308,12 +376,18 @@ HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std:
   DevBuf d_perm;
   upload(d_perm, perm, s);
 
+  // Where each block's values are: a packed device buffer (buf, boff) or
+  // own storage (host fallback); len = k (m + n) or m n doubles.
   struct Result {
     int kind = 0;
     int64_t rank = 0;
-    std::vector<double> a, b;
+    long long len = 0;
+    int buf = -1;
+    long long boff = 0;
+    std::vector<double> own;
   };
   std::vector<Result> res(nb);
+  std::deque<DevBuf> packed_bufs;  // packed factors, one per ACA batch
   std::vector<int64_t> dense_list, host_list;
 
   // --- low-rank candidates, in batches whose scratch fits a share of free memory
@@ -351,9 +425,8 @@ HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std:
     hip_ok(hipMemcpyAsync(rank.data(), d_rank.p, rank.size() * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     hip_ok(hipMemcpyAsync(status.data(), d_status.p, status.size() * sizeof(int), hipMemcpyDeviceToHost, s), "copy");
     hip_ok(hipStreamSynchronize(s), "ACA");
-    // pack the accepted factors and bring them back
+    // pack the accepted factors; they stay on the device until the layout is known
     std::vector<PackBlock> pk;
-    std::vector<int64_t> pk_block;
     long long packed = 0;
     for (size_t q = 0; q < ab.size(); ++q) {
       const int64_t b = lr[p0 + q];
@@ -361,27 +434,23 @@ HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std:
       else if (status[q] == 2) host_list.push_back(b);
       else {
         pk.push_back(PackBlock{ab[q].m, ab[q].n, ab[q].off, packed, rank[q], 0});
-        pk_block.push_back(b);
-        packed += (long long)rank[q] * (ab[q].m + ab[q].n);
+        Result& R = res[b];
+        R.kind = 1;
+        R.rank = rank[q];
+        R.len = (long long)rank[q] * (ab[q].m + ab[q].n);
+        R.buf = R.len > 0 ? (int)packed_bufs.size() : -1;
+        R.boff = packed;
+        packed += R.len;
       }
     }
-    if (!pk.empty()) {
-      DevBuf d_pk, d_out(packed * sizeof(double));
+    if (packed > 0) {
+      DevBuf d_pk;
       upload(d_pk, pk, s);
+      packed_bufs.emplace_back((size_t)packed * sizeof(double));
       hipLaunchKernelGGL(k_pack, dim3((unsigned)pk.size()), dim3(kThreads), 0, s, d_pk.as<PackBlock>(),
-                         d_scratch.as<double>(), d_out.as<double>());
+                         d_scratch.as<double>(), packed_bufs.back().as<double>());
       hip_ok(hipGetLastError(), "pack launch");
-      std::vector<double> host(packed);
-      if (packed) hip_ok(hipMemcpyAsync(host.data(), d_out.p, packed * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
       hip_ok(hipStreamSynchronize(s), "pack");
-      for (size_t q = 0; q < pk.size(); ++q) {
-        Result& R = res[pk_block[q]];
-        R.kind = 1;
-        R.rank = pk[q].k;
-        const double* src = host.data() + pk[q].dst;
-        R.a.assign(src, src + (long long)pk[q].k * pk[q].m);
-        R.b.assign(src + (long long)pk[q].k * pk[q].m, src + (long long)pk[q].k * (pk[q].m + pk[q].n));
-      }
     }
     p0 = p1;
   }
@@ -393,50 +462,20 @@ HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std:
       const BlockSpec& sp = blocks[b];
       int64_t rank = 0;
       if (aca_block(A, tree.perm.data() + sp.r0, sp.m, tree.perm.data() + sp.c0, sp.n, eps, max_rank, U, W, rank)) {
-        res[b].kind = 1;
-        res[b].rank = rank;
-        res[b].a = U;
-        res[b].b = W;
+        Result& R = res[b];
+        R.kind = 1;
+        R.rank = rank;
+        R.own = U;
+        R.own.insert(R.own.end(), W.begin(), W.end());
+        R.len = (long long)R.own.size();
       } else {
         dense_list.push_back(b);
       }
     }
   }
-
-  // --- dense blocks, in batches
-  std::sort(dense_list.begin(), dense_list.end());
-  for (size_t p0 = 0; p0 < dense_list.size();) {
-    std::vector<FillBlock> fb;
-    std::vector<long long> starts;
-    long long tot = 0;
-    size_t p1 = p0;
-    for (; p1 < dense_list.size(); ++p1) {
-      const BlockSpec& sp = blocks[dense_list[p1]];
-      const long long need = (long long)sp.m * sp.n;
-      if (!fb.empty() && tot + need > budget) break;
-      fb.push_back(FillBlock{sp.r0, sp.m, sp.c0, sp.n, tot});
-      starts.push_back(tot);
-      tot += need;
-    }
-    DevBuf d_fb, d_starts, d_out(tot * sizeof(double));
-    upload(d_fb, fb, s);
-    upload(d_starts, starts, s);
-    const long long chunk = (long long)kThreads * 64;
-    hipLaunchKernelGGL(k_fill, dim3((unsigned)((tot + chunk - 1) / chunk)), dim3(kThreads), 0, s, Ed,
-                       d_perm.as<long long>(), d_fb.as<FillBlock>(), d_starts.as<long long>(), (int)fb.size(), tot,
-                       d_out.as<double>());
-    hip_ok(hipGetLastError(), "fill launch");
-    std::vector<double> host(tot);
-    hip_ok(hipMemcpyAsync(host.data(), d_out.p, tot * sizeof(double), hipMemcpyDeviceToHost, s), "copy");
-    hip_ok(hipStreamSynchronize(s), "fill");
-    for (size_t q = 0; q < fb.size(); ++q) {
-      Result& R = res[dense_list[p0 + q]];
-      R.kind = 0;
-      R.rank = 0;
-      R.a.assign(host.data() + fb[q].off, host.data() + fb[q].off + fb[q].m * fb[q].n);
-      R.b.clear();
-    }
-    p0 = p1;
+  for (int64_t b : dense_list) {
+    res[b] = Result{};
+    res[b].len = blocks[b].m * blocks[b].n;
   }
 
   // --- the block list, laid out as the host construction does
@@ -448,17 +487,60 @@ HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std:
   H.off.resize(nb);
   int64_t total = 0;
   for (int64_t b = 0; b < nb; ++b) {
-    H.off[b] = total;
-    total += (int64_t)(res[b].a.size() + res[b].b.size());
-  }
-  H.values.resize(total);
-  for (int64_t b = 0; b < nb; ++b) {
     const BlockSpec& sp = blocks[b];
     int64_t* d = &H.desc[6 * b];
     d[0] = res[b].kind;
     d[1] = sp.r0; d[2] = sp.m; d[3] = sp.c0; d[4] = sp.n; d[5] = res[b].rank;
-    std::copy(res[b].a.begin(), res[b].a.end(), H.values.begin() + H.off[b]);
-    std::copy(res[b].b.begin(), res[b].b.end(), H.values.begin() + H.off[b] + res[b].a.size());
+    H.off[b] = total;
+    total += res[b].len;
+  }
+  H.values.resize(total);
+  Downloader down(s, n_threads);
+
+  // --- packed factors to their places
+  {
+    std::vector<std::vector<Segment>> segs(packed_bufs.size());
+    for (int64_t b = 0; b < nb; ++b)
+      if (res[b].buf >= 0) segs[res[b].buf].push_back(Segment{res[b].boff, res[b].len, H.values.data() + H.off[b]});
+    for (size_t i = 0; i < packed_bufs.size(); ++i) {
+      const long long tot = segs[i].empty() ? 0 : segs[i].back().soff + segs[i].back().len;
+      down.run(packed_bufs[i].as<double>(), tot, segs[i]);
+      packed_bufs[i].reset(0);
+    }
+  }
+  parallel_for(nb, n_threads, [&](int64_t b) {
+    if (!res[b].own.empty()) std::copy(res[b].own.begin(), res[b].own.end(), H.values.begin() + H.off[b]);
+  });
+
+  // --- dense blocks, in batches, evaluated on the device and copied to their places
+  std::sort(dense_list.begin(), dense_list.end());
+  for (size_t p0 = 0; p0 < dense_list.size();) {
+    std::vector<FillBlock> fb;
+    std::vector<long long> starts;
+    std::vector<Segment> segs;
+    long long tot = 0;
+    size_t p1 = p0;
+    for (; p1 < dense_list.size(); ++p1) {
+      const int64_t b = dense_list[p1];
+      const BlockSpec& sp = blocks[b];
+      const long long need = (long long)sp.m * sp.n;
+      if (!fb.empty() && tot + need > budget) break;
+      fb.push_back(FillBlock{sp.r0, sp.m, sp.c0, sp.n, tot});
+      starts.push_back(tot);
+      segs.push_back(Segment{tot, need, H.values.data() + H.off[b]});
+      tot += need;
+    }
+    DevBuf d_fb, d_starts, d_out(tot * sizeof(double));
+    upload(d_fb, fb, s);
+    upload(d_starts, starts, s);
+    const long long chunk = (long long)kThreads * 64;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)((tot + chunk - 1) / chunk)), dim3(kThreads), 0, s, Ed,
+                       d_perm.as<long long>(), d_fb.as<FillBlock>(), d_starts.as<long long>(), (int)fb.size(), tot,
+                       d_out.as<double>());
+    hip_ok(hipGetLastError(), "fill launch");
+    down.run(d_out.as<double>(), tot, segs);
+    hip_ok(hipStreamSynchronize(s), "fill");
+    p0 = p1;
   }
   H.tree_depth = tree.max_depth;
   return H;

@@ -148,8 +148,8 @@ struct hmat_s {
     for (void* p : allocs) (void)hipFree(p);
   }
 
-  template <typename V>
-  V* upload(const std::vector<V>& v, hipStream_t s, bool batched_set = false) {
+  template <typename V, typename Alloc>
+  V* upload(const std::vector<V, Alloc>& v, hipStream_t s, bool batched_set = false) {
     const size_t bytes = std::max<size_t>(sizeof(V), v.size() * sizeof(V));
     void* p = nullptr;
     check_hip(hipMalloc(&p, bytes), "hipMalloc");
@@ -184,7 +184,7 @@ struct hmat_s {
 
   template <typename T>
   void setup_plain(bool transpose, hipStream_t s) {
-    hm::PlainLayout<T> L = hm::make_plain<T>(H, transpose);
+    hm::PlainLayout<T> L = hm::make_plain<T>(H, transpose, opts.n_threads);
     plain.blocks = upload(L.blocks, s);
     plain.lr_list = upload(L.lr_list, s);
     plain.n_lr = (int32_t)L.lr_list.size();
@@ -206,7 +206,7 @@ struct hmat_s {
   // Batched layout of H^T, kept for the life of the handle (fixed set).
   template <typename T>
   void setup_batched_t(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
-    hm::BatchedLayout<T> L = hm::make_batched<T>(hm::transpose_host(H), wg, unit_bytes, wg1);
+    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1, true, opts.n_threads);
     batched_t.units = upload(L.units, s);
     batched_t.n1 = L.n1;
     batched_t.n2 = L.n2;
@@ -224,7 +224,7 @@ struct hmat_s {
 
   template <typename T>
   void setup_batched(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
-    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1);
+    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1, false, opts.n_threads);
     batched.units = upload(L.units, s, true);
     batched.n1 = L.n1;
     batched.n2 = L.n2;
@@ -455,7 +455,7 @@ hmat_status hmat_build(const hmat_mesh* mesh, const hmat_green* green, const hma
     std::vector<hm::BlockSpec> blocks = hm::partition(tree, opts->lattice, opts->eta);
     hm::HostMatrix H =
         opts->build_device
-            ? hm::assemble_device(*E, tree, blocks, opts->aca_eps, opts->max_rank, stream)
+            ? hm::assemble_device(*E, tree, blocks, opts->aca_eps, opts->max_rank, opts->n_threads, stream)
             : hm::assemble(*E, tree, blocks, opts->aca_eps, opts->max_rank, opts->n_threads);
     H.lattice = opts->lattice;
     hmat_t h = create_handle(std::move(H), *opts, static_cast<hipStream_t>(stream));

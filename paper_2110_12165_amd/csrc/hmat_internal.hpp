@@ -1,9 +1,14 @@
 // Internal declarations of the lattice H-matrix library (host side).
 #pragma once
 
+#include <algorithm>
+#include <atomic>
 #include <cstdint>
+#include <new>
 #include <stdexcept>
 #include <string>
+#include <thread>
+#include <utility>
 #include <vector>
 
 #include "entries.hpp"
@@ -18,6 +23,56 @@ struct Error : std::runtime_error {
 };
 
 [[noreturn]] inline void fail(hmat_status c, const std::string& msg) { throw Error(c, msg); }
+
+// Allocator whose value-less construction leaves arithmetic elements
+// uninitialised: large host buffers that are written in full afterwards
+// (by several threads) skip a serial zero fill.
+template <typename T>
+struct NoInitAlloc : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInitAlloc<U>;
+  };
+  NoInitAlloc() = default;
+  template <typename U>
+  NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new (static_cast<void*>(p)) U;
+  }
+  template <typename U, typename... Args>
+  void construct(U* p, Args&&... args) {
+    ::new (static_cast<void*>(p)) U(std::forward<Args>(args)...);
+  }
+};
+template <typename T>
+using HostVec = std::vector<T, NoInitAlloc<T>>;
+
+// Runs f(0 .. count-1) on up to n_threads threads (0: all hardware
+// threads), items handed out one at a time.  f must not throw.
+template <typename F>
+void parallel_for(int64_t count, int32_t n_threads, F&& f) {
+  int64_t nt = n_threads > 0 ? n_threads : (int64_t)std::max(1u, std::thread::hardware_concurrency());
+  nt = std::max<int64_t>(1, std::min<int64_t>(nt, count));
+  std::atomic<int64_t> next{0};
+  auto work = [&] {
+    for (int64_t k; (k = next.fetch_add(1)) < count;) f(k);
+  };
+  std::vector<std::thread> th;
+  for (int64_t t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+}
+
+// Sets v[0 .. size) to zero in chunks spread over threads.
+template <typename T>
+void parallel_zero(T* v, int64_t size, int32_t n_threads) {
+  constexpr int64_t kChunk = 1 << 18;
+  parallel_for((size + kChunk - 1) / kChunk, n_threads, [&](int64_t c) {
+    const int64_t a = c * kChunk, b = std::min(size, a + kChunk);
+    std::fill(v + a, v + b, T(0));
+  });
+}
 
 // ---------------------------------------------------------------------------
 // Geometry and stiffness entries (eqs. (5)-(6)).
@@ -78,7 +133,7 @@ struct HostMatrix {
   std::vector<int32_t> perm;
   std::vector<int64_t> desc;    // 6 per block: kind, r0, m, c0, n, rank
   std::vector<int64_t> off;     // per block
-  std::vector<double> values;
+  HostVec<double> values;
   int32_t lattice = 1;
   int32_t tree_depth = 0;
   int64_t nblocks() const { return (int64_t)off.size(); }
@@ -97,9 +152,10 @@ HostMatrix assemble(const EntryFn& A, const ClusterTree& tree, const std::vector
 // The same block list built on the device (build_gpu.hip): ACA of the
 // admissible blocks and entries of the dense ones on the GPU, with the rules
 // of assemble(); blocks beyond the device rank cap go through aca_block().
-// stream: a hipStream_t (or null).
+// n_threads: threads of the host-side steps (0: all); stream: a
+// hipStream_t (or null).
 HostMatrix assemble_device(const EntryFn& A, const ClusterTree& tree, const std::vector<BlockSpec>& blocks,
-                           double eps, int32_t max_rank, void* stream);
+                           double eps, int32_t max_rank, int32_t n_threads, void* stream);
 
 // Checks that blocks tile the matrix once and perm is a permutation.
 void validate_host_matrix(const HostMatrix& H);

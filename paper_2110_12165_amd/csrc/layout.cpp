@@ -14,6 +14,35 @@ int64_t align_elems(int64_t off) {
   return (off + a - 1) / a * a;
 }
 
+// Block b of H, or of H^T with tr set (rows and columns exchanged, the dense
+// part transposed, U and V exchanged), read in place.
+struct BlockView {
+  const HostMatrix& H;
+  bool tr;
+  const int64_t* d(int64_t b) const { return &H.desc[6 * b]; }
+  int64_t kind(int64_t b) const { return d(b)[0]; }
+  int64_t r0(int64_t b) const { return d(b)[tr ? 3 : 1]; }
+  int64_t m(int64_t b) const { return d(b)[tr ? 4 : 2]; }
+  int64_t c0(int64_t b) const { return d(b)[tr ? 1 : 3]; }
+  int64_t n(int64_t b) const { return d(b)[tr ? 2 : 4]; }
+  int64_t rank(int64_t b) const { return d(b)[5]; }
+  // Column j of the dense block as (first entry, stride between rows).
+  std::pair<const double*, int64_t> dense_col(int64_t b, int64_t j) const {
+    const double* v = &H.values[H.off[b]];
+    const int64_t mh = d(b)[2];
+    return tr ? std::make_pair(v + j, mh) : std::make_pair(v + j * mh, (int64_t)1);
+  }
+  // Column kk of U (length m) and of V (length n), contiguous.
+  const double* u_col(int64_t b, int64_t kk) const {
+    const double* v = &H.values[H.off[b]];
+    return tr ? v + d(b)[2] * d(b)[5] + kk * d(b)[4] : v + kk * d(b)[2];
+  }
+  const double* v_col(int64_t b, int64_t kk) const {
+    const double* v = &H.values[H.off[b]];
+    return tr ? v + kk * d(b)[2] : v + d(b)[2] * d(b)[5] + kk * d(b)[4];
+  }
+};
+
 inline int32_t to_i32(int64_t v, const char* what) {
   if (v < 0 || v > INT32_MAX) fail(HMAT_EUNSUPPORTED, std::string(what) + " exceeds the 32-bit range of the layout");
   return (int32_t)v;
@@ -76,7 +105,7 @@ HostMatrix transpose_host(const HostMatrix& H) {
   T.desc.resize(6 * nb);
   T.off = H.off;
   T.values.resize(H.values.size());
-  for (int64_t b = 0; b < nb; ++b) {
+  parallel_for(nb, 0, [&](int64_t b) {
     const int64_t* d = &H.desc[6 * b];
     int64_t* e = &T.desc[6 * b];
     const int64_t m = d[2], n = d[4], r = d[5];
@@ -95,12 +124,12 @@ HostMatrix transpose_host(const HostMatrix& H) {
       std::copy(v + m * r, v + (m + n) * r, w);      // U' = V (n x r)
       std::copy(v, v + m * r, w + n * r);            // V' = U (m x r)
     }
-  }
+  });
   return T;
 }
 
 template <typename T>
-PlainLayout<T> make_plain(const HostMatrix& H, bool transpose) {
+PlainLayout<T> make_plain(const HostMatrix& H, bool transpose, int32_t n_threads) {
   PlainLayout<T> L;
   const int64_t nb = H.nblocks();
   L.blocks.resize(nb);
@@ -130,8 +159,9 @@ PlainLayout<T> make_plain(const HostMatrix& H, bool transpose) {
     }
   }
   L.sum_rank = tslot;
-  L.pool.assign(align_elems<T>(off) + 256 / sizeof(T), T(0));
-  for (int64_t b = 0; b < nb; ++b) {
+  L.pool.resize(align_elems<T>(off) + 256 / sizeof(T));
+  parallel_zero(L.pool.data(), (int64_t)L.pool.size(), n_threads);
+  parallel_for(nb, n_threads, [&](int64_t b) {
     const int64_t* d = &H.desc[6 * b];
     const double* v = &H.values[H.off[b]];
     const PlainBlock& p = L.blocks[b];
@@ -141,7 +171,7 @@ PlainLayout<T> make_plain(const HostMatrix& H, bool transpose) {
       for (int64_t k = 0; k < d[2] * d[5]; ++k) L.pool[p.offA + k] = (T)v[k];
       for (int64_t k = 0; k < d[4] * d[5]; ++k) L.pool[p.offB + k] = (T)v[d[2] * d[5] + k];
     }
-  }
+  });
   for (int pass = 0; pass < (transpose ? 2 : 1); ++pass) {
     Incidence I = incidence(H, pass == 1, 64);
     auto& units = pass == 0 ? L.row_units : L.col_units;
@@ -164,13 +194,15 @@ PlainLayout<T> make_plain(const HostMatrix& H, bool transpose) {
 }
 
 template <typename T>
-BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1) {
+BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1,
+                              bool transpose, int32_t n_threads) {
   constexpr int W = 16 / (int)sizeof(T);
   BatchedLayout<T> L;
   L.wg_waves = wg_waves;
   L.wg_waves_p1 = wg_waves_p1;
   L.unit_bytes = unit_bytes;
   const int64_t nb = H.nblocks();
+  const BlockView B{H, transpose};
 
   // ---- phase 1: group low-rank blocks by their column cluster -------------
   // Every unit covers all rows of its cluster, so each intermediate value is
@@ -187,16 +219,15 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
   std::vector<Group> groups;
   std::map<std::pair<int64_t, int64_t>, size_t> gid;
   for (int64_t b = 0; b < nb; ++b) {
-    const int64_t* d = &H.desc[6 * b];
-    if (d[0] != 1 || d[5] == 0) continue;
-    auto key = std::make_pair(d[3], d[4]);
+    if (B.kind(b) != 1 || B.rank(b) == 0) continue;
+    auto key = std::make_pair(B.c0(b), B.n(b));
     auto it = gid.find(key);
     if (it == gid.end()) {
       it = gid.emplace(key, groups.size()).first;
-      groups.push_back(Group{d[3], d[4], {}, 0, 0, 1, 1});
+      groups.push_back(Group{B.c0(b), B.n(b), {}, 0, 0, 1, 1});
     }
     groups[it->second].blocks.push_back((int32_t)b);
-    groups[it->second].R += d[5];
+    groups[it->second].R += B.rank(b);
   }
   std::vector<int64_t> slot_of_block(nb, -1);  // t index of (block, column 0)
   int64_t t = 1;                                // t[0] is the zero pad
@@ -212,13 +243,12 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     g.base = t;
     for (int32_t b : g.blocks) {
       slot_of_block[b] = t;
-      t += H.desc[6 * b + 5];
+      t += B.rank(b);
     }
   }
   L.t_size = t;
   to_i32(t + 1, "intermediate values");
 
-  std::vector<Unit> p1, p2;
   struct Pending { Unit u; int kind; size_t g; int64_t s0; };
   int64_t off = 0;
   std::vector<Pending> pend;
@@ -241,7 +271,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     }
   }
   // ---- phase 2: one unit per refined row interval --------------------------
-  Incidence I = incidence(H, false, 64);
+  Incidence I = incidence(H, transpose, 64);
   for (size_t k = 0; k < I.iv.size(); ++k) {
     const int64_t a = I.iv[k].first, m = I.iv[k].second - I.iv[k].first;
     Unit u;
@@ -255,13 +285,13 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     // dense columns first, then low-rank columns
     for (int pass = 0; pass < 2; ++pass)
       for (auto& e : I.members[k]) {
-        const int64_t* d = &H.desc[6 * e.first];
-        if (pass == 0 && d[0] == 0) {
-          for (int64_t j = 0; j < d[4]; ++j) L.src.push_back(H.perm[d[3] + j]);
-          K += d[4];
-        } else if (pass == 1 && d[0] == 1 && d[5] > 0) {
-          for (int64_t kk = 0; kk < d[5]; ++kk) L.src.push_back(-(int32_t)(slot_of_block[e.first] + kk) - 1);
-          K += d[5];
+        const int64_t b = e.first;
+        if (pass == 0 && B.kind(b) == 0) {
+          for (int64_t j = 0; j < B.n(b); ++j) L.src.push_back(H.perm[B.c0(b) + j]);
+          K += B.n(b);
+        } else if (pass == 1 && B.kind(b) == 1 && B.rank(b) > 0) {
+          for (int64_t kk = 0; kk < B.rank(b); ++kk) L.src.push_back(-(int32_t)(slot_of_block[b] + kk) - 1);
+          K += B.rank(b);
         }
       }
     while (K % W) {
@@ -286,57 +316,58 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     p.u.off = off = align_elems<T>(off);
     off += (int64_t)p.u.nq * W * p.u.nout;
   }
-  L.pool.assign(align_elems<T>(off) + 256 / sizeof(T), T(0));
+  L.pool.resize(align_elems<T>(off) + 256 / sizeof(T));
+  parallel_zero(L.pool.data(), (int64_t)L.pool.size(), n_threads);
 
-  // ---- fill panels ----------------------------------------------------------
-  for (auto& p : pend) {
+  // ---- fill panels (units own disjoint pool ranges) -------------------------
+  parallel_for((int64_t)pend.size(), n_threads, [&](int64_t pi) {
+    const Pending& p = pend[pi];
     const Unit& u = p.u;
     T* dst = &L.pool[u.off];
     if (p.kind == 1) {
       const Group& g = groups[p.g];
-      // map local slots of this unit to (block, column)
-      std::vector<std::pair<int32_t, int64_t>> sl(u.nout);
+      // local output slot o of this unit -> column of V of one block
+      std::vector<const double*> sl(u.nout);
       {
         int64_t s = 0, o = 0;
-        for (int32_t b : g.blocks) {
-          const int64_t r = H.desc[6 * b + 5];
-          for (int64_t kk = 0; kk < r; ++kk, ++s)
-            if (s >= p.s0 && s < p.s0 + u.nout) sl[o++] = {b, kk};
-        }
+        for (int32_t b : g.blocks)
+          for (int64_t kk = 0; kk < B.rank(b); ++kk, ++s)
+            if (s >= p.s0 && s < p.s0 + u.nout) sl[o++] = B.v_col(b, kk);
       }
       for (int64_t q = 0; q < u.nq; ++q)
         for (int64_t o = 0; o < u.nout; ++o) {
-          const int32_t b = sl[o].first;
-          const int64_t kk = sl[o].second;
-          const int64_t m = H.desc[6 * b + 2], n = H.desc[6 * b + 4], r = H.desc[6 * b + 5];
-          const double* V = &H.values[H.off[b] + m * r];
+          const double* V = sl[o];
           for (int c = 0; c < W; ++c) {
             const int64_t j = q * W + c;
-            dst[(q * u.nout + o) * W + c] = j < u.nin ? (T)V[kk * n + j] : T(0);
+            dst[(q * u.nout + o) * W + c] = j < u.nin ? (T)V[j] : T(0);
           }
         }
     } else {
       const int64_t m = u.nout;
       int64_t col = 0;
-      auto put = [&](const double* colv) {  // colv[i] = coefficient of row i
+      // colv[i * stride] = coefficient of row i of this unit
+      auto put = [&](const double* colv, int64_t stride) {
         const int64_t q = col / W, c = col % W;
-        for (int64_t o = 0; o < m; ++o) dst[(q * m + o) * W + c] = colv ? (T)colv[o] : T(0);
+        for (int64_t o = 0; o < m; ++o) dst[(q * m + o) * W + c] = colv ? (T)colv[o * stride] : T(0);
         ++col;
       };
       for (int pass = 0; pass < 2; ++pass)
         for (auto& e : I.members[p.g]) {
-          const int64_t* d = &H.desc[6 * e.first];
-          const double* v = &H.values[H.off[e.first]];
-          if (pass == 0 && d[0] == 0) {
-            for (int64_t j = 0; j < d[4]; ++j) put(v + j * d[2] + e.second);
-          } else if (pass == 1 && d[0] == 1 && d[5] > 0) {
-            for (int64_t kk = 0; kk < d[5]; ++kk) put(v + kk * d[2] + e.second);
+          const int64_t b = e.first, i0 = e.second;
+          if (pass == 0 && B.kind(b) == 0) {
+            for (int64_t j = 0; j < B.n(b); ++j) {
+              const auto cs = B.dense_col(b, j);
+              put(cs.first + i0 * cs.second, cs.second);
+            }
+          } else if (pass == 1 && B.kind(b) == 1 && B.rank(b) > 0) {
+            for (int64_t kk = 0; kk < B.rank(b); ++kk) put(B.u_col(b, kk) + i0, 1);
           }
         }
-      while (col % W) put(nullptr);
+      while (col % W) put(nullptr, 0);
     }
-    (p.kind == 1 ? p1 : p2).push_back(u);
-  }
+  });
+  std::vector<Unit> p1, p2;
+  for (auto& p : pend) (p.kind == 1 ? p1 : p2).push_back(p.u);
   L.n1 = (int32_t)p1.size();
   L.n2 = (int32_t)p2.size();
   L.units = std::move(p1);
@@ -344,9 +375,9 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
   return L;
 }
 
-template PlainLayout<float> make_plain<float>(const HostMatrix&, bool);
-template PlainLayout<double> make_plain<double>(const HostMatrix&, bool);
-template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t, int32_t);
-template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t, int32_t);
+template PlainLayout<float> make_plain<float>(const HostMatrix&, bool, int32_t);
+template PlainLayout<double> make_plain<double>(const HostMatrix&, bool, int32_t);
+template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t);
+template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t);
 
 }  // namespace hm

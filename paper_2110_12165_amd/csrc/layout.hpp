@@ -12,7 +12,7 @@ namespace hm {
 // Natural layout: blocks as built, each starting on a 256-byte boundary.
 template <typename T>
 struct PlainLayout {
-  std::vector<T> pool;
+  HostVec<T> pool;
   std::vector<PlainBlock> blocks;
   std::vector<int32_t> lr_list;        // low-rank blocks with rank > 0
   std::vector<RowUnit> row_units;      // owners of output rows (product)
@@ -23,13 +23,13 @@ struct PlainLayout {
 };
 
 template <typename T>
-PlainLayout<T> make_plain(const HostMatrix& H, bool transpose);
+PlainLayout<T> make_plain(const HostMatrix& H, bool transpose, int32_t n_threads = 0);
 
 // Batched layout: every product becomes a list of work units over packed
 // panels (see Unit in device_types.hpp).
 template <typename T>
 struct BatchedLayout {
-  std::vector<T> pool;
+  HostVec<T> pool;
   std::vector<Unit> units;             // n1 phase-1 units, then n2 phase-2 units
   int32_t n1 = 0, n2 = 0;
   std::vector<int32_t> src;
@@ -41,8 +41,11 @@ struct BatchedLayout {
 
 // wg_waves: waves per workgroup of phase-2 units; wg_waves_p1: of phase-1
 // units (equal for the persistent schedule, which runs both in one launch).
+// transpose: pack H^T (read in place; the same layout as packing
+// transpose_host(H)).  n_threads: panel-filling threads, 0 for all.
 template <typename T>
-BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1);
+BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1,
+                              bool transpose = false, int32_t n_threads = 0);
 
 // The blocks of H^T (dense blocks transposed, U and V exchanged), same
 // permutation: packing them gives the layouts of the transpose product.

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <memory>
 #include <vector>
 
@@ -195,6 +196,16 @@ int main(int argc, char** argv) {
   }
   for (int64_t i = 0; i < n; ++i) yrefT[H.perm[i]] = ycT[i];
   const HostMatrix HT = transpose_host(H);
+  // packing H^T in place gives the same layout as packing the transposed copy
+  for (int NW1 : {4, 8}) {
+    const BatchedLayout<float> a = make_batched<float>(HT, 8, 256 << 10, NW1);
+    const BatchedLayout<float> b = make_batched<float>(H, 8, 256 << 10, NW1, true, 3);
+    if (a.pool != b.pool || a.src != b.src || a.n1 != b.n1 || a.n2 != b.n2 || a.t_size != b.t_size ||
+        a.units.size() != b.units.size())
+      die("in-place transpose packing differs", NW1);
+    for (size_t k = 0; k < a.units.size(); ++k)
+      if (std::memcmp(&a.units[k], &b.units[k], sizeof(Unit)) != 0) die("in-place transpose unit differs", (long)k);
+  }
   for (int NW : {4, 8}) {
     const double r64 = replay<double>(HT, NW, 4, 256 << 10, x, yrefT);
     const double r32 = replay<float>(HT, NW, 4, 256 << 10, x, yrefT);
