@@ -385,6 +385,45 @@ def construction(torch, hm, f, opts, x):
     return out
 
 
+def sweeps(torch, hm, steps=50, warmup=5):
+    """Stored entries, build time and FP32 product time of the benchmark
+    fault against N (four sizes, lattice 32) and against the lattice size at
+    N = 122880 (lattice 1: the normal H-matrix).  Device construction,
+    no transposed layout."""
+    from synth import LATTICE_SWEEP, SIZE_SWEEP, WORKLOADS, config_fault, loguniform_rates
+    from synth.faults import MU, NU
+    dev = torch.device("cuda:0")
+
+    def one(name, lattice):
+        w = WORKLOADS[name]
+        f = config_fault(name)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
+                             lattice=lattice, prec="f32", kernel="split", transpose=0, build_device=1)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - t0
+        info = H.info()
+        x = torch.tensor(loguniform_rates(f.n, w["seed"]), device=dev)
+        y = torch.empty_like(x)
+        ms, _, _ = time_products(torch, H, x, y, steps, warmup)
+        H.close()
+        torch.cuda.empty_cache()
+        entries = info["dense_entries"] + info["lr_entries"]
+        r = dict(workload=name, N=f.n, lattice=lattice, build_s=build_s, stored_frac=entries / float(f.n) ** 2,
+                 factor_gb=info["factor_bytes"] / 1e9, n_lr=info["n_lr"], n_dense=info["n_dense"],
+                 max_rank=info["max_rank"], us_per_product=ms * 1e3,
+                 gbs=info["alg_bytes"] / (ms * 1e-3) / 1e9)
+        log(f"[bench] sweep {name} lattice {lattice}: N={f.n}, stored {100 * r['stored_frac']:.2f} %, "
+            f"{r['factor_gb']:.3f} GB, build {build_s:.2f} s, {r['us_per_product']:.1f} us/product "
+            f"({r['gbs']:.0f} GB/s)")
+        return r
+
+    out = {"size": [one(name, WORKLOADS[name]["lattice"]) for name in SIZE_SWEEP]}
+    out["lattice"] = [one("dip30_480x256", L) for L in LATTICE_SWEEP]
+    return out
+
+
 def adjoint_run(torch, hm, n_steps, ckpt_every=50):
     """Gradient of the final-slip misfit L = 1/2 |D_M - D_target|^2 for
     per-element a (b fixed) and d_c on the N = 21000 mesh with FP32 factors:
@@ -485,6 +524,7 @@ def main():
                     help="workloads of the 64-member MFMA ensemble product ('' to skip)")
     ap.add_argument("--no-nonplanar", action="store_true", help="skip the triangle-mesh section")
     ap.add_argument("--no-construction", action="store_true", help="skip the host/device build timing")
+    ap.add_argument("--no-sweeps", action="store_true", help="skip the size and lattice sweeps")
     ap.add_argument("--ens-rk-steps", type=int, default=100,
                     help="steps per member of the ensemble integration (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
@@ -601,6 +641,8 @@ def main():
         line["rel_diff_f32_vs_f64_gpu"] = float(np.linalg.norm(outputs["batched_f32"] - ref) / np.linalg.norm(ref))
     if not args.no_construction:
         line["construction"] = construction(torch, hm, f, bench_options(WORKLOAD, "batched_f32"), x)
+    if not args.no_sweeps:
+        line["sweeps"] = sweeps(torch, hm)
     if args.rk_steps > 0:
         line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
     if args.ensemble:

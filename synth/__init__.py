@@ -14,6 +14,8 @@ from .faults import (  # noqa: F401
     friction_params,
     ensemble_params,
     WORKLOADS,
+    SIZE_SWEEP,
+    LATTICE_SWEEP,
     TriangleFault,
     curved_thrust_fault,
     config_triangle_fault,

@@ -107,7 +107,20 @@ WORKLOADS = {
     # used for many-member runs), planar stand-in, 64 members
     "dip30_150x140": dict(mesh=(150, 140, 100.0, 30.0, "dip"),
                           aca_eps=1e-6, leaf=32, eta=2.0, lattice=8, seed=3),
+    # the benchmark fault at other sizes (same element size and options)
+    "dip30_120x64": dict(mesh=(120, 64, 50.0, 30.0, "dip"),
+                         aca_eps=1e-5, leaf=64, eta=2.0, lattice=32, seed=21),
+    "dip30_240x128": dict(mesh=(240, 128, 50.0, 30.0, "dip"),
+                          aca_eps=1e-5, leaf=64, eta=2.0, lattice=32, seed=22),
+    "dip30_960x512": dict(mesh=(960, 512, 50.0, 30.0, "dip"),
+                          aca_eps=1e-5, leaf=64, eta=2.0, lattice=32, seed=23),
 }
+
+# Stored entries and product time against N (the paper's memory and time
+# studies, section 4), and against the lattice size at N = 122880, where
+# lattice 1 is the normal H-matrix.
+SIZE_SWEEP = ("dip30_120x64", "dip30_240x128", "dip30_480x256", "dip30_960x512")
+LATTICE_SWEEP = (1, 8, 32)
 
 
 def config_fault(name: str) -> PlanarRectFault:
