@@ -110,7 +110,7 @@ typedef struct {
   int32_t max_rank;        /* rank cap before the dense fallback; 0 = min(m, n) / 2 */
   int32_t prec;            /* hmat_prec: factor storage on the device */
   int32_t kernel;          /* hmat_kernel */
-  int32_t n_threads;       /* host threads for the build; 0 = all hardware threads */
+  int32_t n_threads;       /* host threads for construction and packing; 0 = every CPU of the process affinity mask */
   int32_t wg_waves;        /* BATCHED: waves per workgroup (4, 8 or 16); 0 = default */
   int32_t unit_kib;        /* BATCHED: target bytes per work unit in KiB; 0 = default */
   int32_t wg_waves_p1;     /* BATCHED split: waves per workgroup of phase 1 (4, 8, 16);

@@ -129,7 +129,7 @@ HostMatrix assemble(const EntryFn& A, const ClusterTree& tree, const std::vector
       err = e.what();
     }
   };
-  int nt = n_threads > 0 ? n_threads : (int)std::max(1u, std::thread::hardware_concurrency());
+  int nt = n_threads > 0 ? n_threads : host_threads();
   nt = (int)std::min<int64_t>(nt, std::max<int64_t>(1, nb));
   std::vector<std::thread> th;
   for (int t = 1; t < nt; ++t) th.emplace_back(work);

@@ -5,6 +5,7 @@
 #include <atomic>
 #include <cstdint>
 #include <new>
+#include <sched.h>
 #include <stdexcept>
 #include <string>
 #include <thread>
@@ -48,11 +49,19 @@ struct NoInitAlloc : std::allocator<T> {
 template <typename T>
 using HostVec = std::vector<T, NoInitAlloc<T>>;
 
-// Runs f(0 .. count-1) on up to n_threads threads (0: all hardware
-// threads), items handed out one at a time.  f must not throw.
+// Threads this process may run on (its CPU affinity mask), at least 1.
+inline int32_t host_threads() {
+  cpu_set_t set;
+  CPU_ZERO(&set);
+  if (sched_getaffinity(0, sizeof(set), &set) == 0) return std::max(1, CPU_COUNT(&set));
+  return (int32_t)std::max(1u, std::thread::hardware_concurrency());
+}
+
+// Runs f(0 .. count-1) on up to n_threads threads (0: host_threads()),
+// items handed out one at a time.  f must not throw.
 template <typename F>
 void parallel_for(int64_t count, int32_t n_threads, F&& f) {
-  int64_t nt = n_threads > 0 ? n_threads : (int64_t)std::max(1u, std::thread::hardware_concurrency());
+  int64_t nt = n_threads > 0 ? n_threads : host_threads();
   nt = std::max<int64_t>(1, std::min<int64_t>(nt, count));
   std::atomic<int64_t> next{0};
   auto work = [&] {
