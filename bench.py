@@ -529,7 +529,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="batched_f32,plain_f64,batched_f64")
-    ap.add_argument("--rk-steps", type=int, default=50,
+    ap.add_argument("--rk-steps", type=int, default=1000,
                     help="accepted RK45 steps of the rate-and-state simulation on the same fault (0: skip)")
     ap.add_argument("--ensemble", default="dip30_150x140,dip30_480x256",
                     help="workloads of the 64-member MFMA ensemble product ('' to skip)")
