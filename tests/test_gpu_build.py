@@ -64,3 +64,28 @@ def test_device_build_matches_host_build(name, component):
     say(f"   rel vs dense: host {rel(yh, y):.2e}, device {rel(yd, y):.2e}")
     assert rel(yd, y) <= 10 * w["aca_eps"]
     assert rel(yd, yh) <= 20 * w["aca_eps"]
+
+
+@pytest.mark.parametrize("nx,ny,lattice,leaf", [(3, 2, 1, 1), (1, 1, 1, 1), (9, 7, 2, 4)])
+def test_device_build_small_and_transpose(nx, ny, lattice, leaf):
+    """Degenerate sizes (a single element, all-dense matrices, ragged
+    leaves) and the FP32 transposed layout of a device-built matrix: H x and
+    H^T x against the dense products of the closed-form entries."""
+    import torch
+
+    import paper_2110_12165_amd as hm
+    from synth import planar_rect_fault
+    f = planar_rect_fault(nx, ny, 100.0, 30.0, "dip")
+    say(f"[device build] {nx}x{ny} lattice {lattice} leaf {leaf}")
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=1e-8, eta=2.0, leaf=leaf, lattice=lattice,
+                         prec="f32", kernel="split", build_device=1)
+    n = f.n
+    x = loguniform_rates(n, 5)
+    xd = torch.tensor(x, device="cuda:0")
+    y = H.matvec(xd).cpu().numpy()
+    yt = H.matvec_T(xd).cpu().numpy()
+    H.close()
+    rows, cols = np.meshgrid(np.arange(n), np.arange(n), indexing="ij")
+    D = hm.kernel_entries(f.verts, f.slip_dir, MU, NU, rows.ravel(), cols.ravel(), 0).reshape(n, n)
+    assert rel(y, D @ x) <= 1e-6
+    assert rel(yt, D.T @ x) <= 1e-6
