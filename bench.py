@@ -303,7 +303,7 @@ def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4):
                     "graph-replayed attempts; single runs use the FP32 single-vector product"}
 
 
-def nonplanar(torch, hm, reps=50):
+def nonplanar(torch, hm, reps=50, rk_steps=500):
     """Curved thrust fault of 21000 triangles (dip 30 +/- 10 degrees down dip):
     shear (A) and normal (B) matrices, FP32-batched against FP64-plain."""
     from synth import TRIANGLE_WORKLOADS, config_triangle_fault, loguniform_rates
@@ -364,7 +364,50 @@ def nonplanar(torch, hm, reps=50):
             f"rel {res['rel_diff_f32_vs_f64']:.1e}, stored {100 * res['stored_fraction']:.1f} % of dense, "
             f"build {res['f32_split']['build_s']:.2f} s host, {res['f32_split']['build_device_s']:.2f} s device "
             f"(products differ by {res['rel_diff_device_vs_host_build']:.1e})")
+    out["rk45"] = nonplanar_rk(torch, hm, f, w, rk_steps)
     torch.cuda.empty_cache()
+    return out
+
+
+def nonplanar_rk(torch, hm, f, w, n_steps):
+    """Rate-and-state run on the nonplanar fault with both products: the
+    shear stress through A and the normal stress through B (eqs. 9-12),
+    FP32 factors built on the device, graph-replayed attempts, from steady
+    state at log-uniform slip rates."""
+    from synth import loguniform_rates, triangle_friction_params
+    from synth.faults import MU, NU
+
+    p = triangle_friction_params(f)
+    dev = torch.device("cuda:0")
+    opts = dict(aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"], prec="f32",
+                kernel="split", build_device=1, transpose=0)
+    HA = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=0, **opts)
+    HB = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=1, **opts)
+    a, b, dc = (torch.tensor(p[k], device=dev) for k in ("a", "b", "dc"))
+    V = loguniform_rates(f.n, w["seed"])
+    phi = p["f0"] + p["b"] * np.log(p["V0"] / V)
+    tau = p["a"] * p["sigma"] * np.arcsinh(V / (2 * p["V0"]) * np.exp(phi / p["a"]))
+    y = torch.tensor(np.concatenate([phi, tau, p["sigma"]]), device=dev)
+    D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    rk = hm.RK45(HA, HB, a, b, dc, p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rk.run(y, D, 2, use_graph=True, stream=s)          # capture + warm-up
+        s.synchronize()
+        t_sim0, acc0, rej0 = rk.t, rk.state.accepted, rk.state.rejected
+        t0 = time.perf_counter()
+        rk.run(y, D, n_steps, use_graph=True, stream=s)
+        s.synchronize()
+        wall = time.perf_counter() - t0
+    attempts = (rk.state.accepted - acc0) + (rk.state.rejected - rej0)
+    sig = y[2 * f.n:].cpu().numpy()
+    HA.close()
+    HB.close()
+    out = {"accepted_steps": n_steps, "attempts": attempts, "wall_s": wall, "steps_per_s": n_steps / wall,
+           "simulated_s": rk.t - t_sim0, "simulated_s_per_wall_s": (rk.t - t_sim0) / wall, "dt_last": rk.dt,
+           "sigma_change_max_pa": float(np.max(np.abs(sig - p["sigma"])))}
+    log(f"[bench] nonplanar rk45 (A and B): {n_steps} steps, {attempts} attempts in {wall:.3f} s, simulated "
+        f"{out['simulated_s']:.3e} s; normal stress moved by up to {out['sigma_change_max_pa']:.3e} Pa")
     return out
 
 
