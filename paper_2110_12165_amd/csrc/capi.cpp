@@ -617,9 +617,12 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
     Free fy{y};
     std::vector<double> ones(n, 1e-9);
     check_hip(hipMemcpy(x, ones.data(), n * sizeof(double), hipMemcpyHostToDevice), "hipMemcpy");
-    hipEvent_t e0, e1;
-    check_hip(hipEventCreate(&e0), "hipEventCreate");
-    check_hip(hipEventCreate(&e1), "hipEventCreate");
+    struct Ev {
+      hipEvent_t e = nullptr;
+      Ev() { check_hip(hipEventCreate(&e), "hipEventCreate"); }
+      ~Ev() { (void)hipEventDestroy(e); }
+    } ev0, ev1;
+    const hipEvent_t e0 = ev0.e, e1 = ev1.e;
     auto time_it = [&](int32_t kern) {
       for (int w = 0; w < 2; ++w) check_hip(h->product(false, x, y, 1.0, 0.0, s, kern), "product launch");
       check_hip(hipEventRecord(e0, s), "hipEventRecord");
@@ -652,8 +655,6 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
           }
         }
     h->kernel = saved_kernel;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     h->drop_batched();
     h->kernel = best_k;
     if (best_k != HMAT_KERNEL_PLAIN) h->setup_batched_any(best_w, (int64_t)best_u * 1024, best_w1, s);

@@ -183,3 +183,33 @@ def test_zero_matrix_keeps_beta_y(torch_dev, hm):
         Hb.matvec(torch.ones(f.n, dtype=torch.float64, device=dev), y=y, alpha=1.0, beta=2.0)
         assert torch.equal(y, 2.0 * y0)
         Hb.close()
+
+
+def test_autotune_and_profile(torch_dev, hm):
+    """hmat_autotune picks a schedule among the candidates and keeps the
+    products (and the transposed ones) within rounding of the oracle;
+    hmat_profile reports one timing and byte count per launch (factors of
+    the launch plus the vectors it reads and writes)."""
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case("dip30_150x70")
+    B = oracle_blocks(H)
+    x = loguniform_rates(f.n, 9)
+    xd = torch.tensor(x, device=dev)
+    ref, ref_t = H.matvec(x), H.matvec_T(x)
+    Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec="f64", kernel="auto")
+    info = Hg.autotune(reps=3)
+    say(f"[autotune] dip30_150x70: kernel {info['kernel']}, waves {info['wg_waves']} / {info['wg_waves_p1']}")
+    assert info["kernel"] in ("plain", "split", "persistent")
+    assert rel(Hg.matvec(xd).cpu().numpy(), ref) <= 1e-13
+    assert rel(Hg.matvec_T(xd).cpu().numpy(), ref_t) <= 1e-13
+    y = torch.empty_like(xd)
+    pr = Hg.profile(xd, y, reps=5)
+    assert pr["n_launches"] in (1, 2) and pr["reps"] == 5
+    assert all(m > 0.0 for m in pr["ms"]) and pr["ms_product"] > 0.0
+    st = Hg.info()
+    if pr["n_launches"] == 2:   # phase 1 and phase 2 each count the vectors they touch
+        assert sum(pr["alg_bytes"]) == st["factor_bytes"] + 40 * st["n"] + 16 * st["sum_rank"]
+    else:
+        assert pr["alg_bytes"][0] == st["alg_bytes"]
+    assert rel(y.cpu().numpy(), ref) <= 1e-13
+    Hg.close()
