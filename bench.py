@@ -637,6 +637,22 @@ def main():
                                 alg_bytes=info["alg_bytes"], achieved_gbs=achieved, dominant_launch=dom,
                                 launches=launches, hbm_frac=achieved / HBM_PEAK_GBS,
                                 product_gbs=whole, product_hbm_frac=whole / HBM_PEAK_GBS, build_s=build_s, info=info)
+        if variant == "batched_f32":
+            # the transposed product (hmat_matvec_T) on its own packed copy of the factors
+            for _ in range(args.warmup):
+                H.matvec_T(x, y=y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                H.matvec_T(x, y=y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_t = e0.elapsed_time(e1) / args.steps
+            results[variant]["transpose"] = dict(ms=ms_t, matvec_per_s=1e3 / ms_t,
+                                                 product_gbs=info["alg_bytes"] / (ms_t * 1e-3) / 1e9)
+            log(f"[bench] {variant}: transposed product {ms_t * 1e3:.1f} us "
+                f"({info['alg_bytes'] / (ms_t * 1e-3) / 1e9:.0f} GB/s)")
         log(f"[bench] {variant}: {1e3 / ms:.1f} matvec/s ({ms * 1e3:.1f} us/product, {whole:.0f} GB/s = "
             f"{100 * whole / HBM_PEAK_GBS:.1f}% of HBM over the product); launches "
             + ", ".join(f"{l['ms'] * 1e3:.1f} us {l['achieved_gbs']:.0f} GB/s" for l in launches))
@@ -688,6 +704,8 @@ def main():
         line[v] = {k: r[k] for k in ("matvec_per_s", "ms", "product_gbs", "product_hbm_frac", "achieved_gbs",
                                      "hbm_frac", "build_s")}
         line[v]["kernel"] = r["info"]["kernel"]
+        if "transpose" in r:
+            line[v]["transpose"] = r["transpose"]
     if "plain_f64" in results:
         line["speedup_batched_f32_vs_plain_f64"] = head["matvec_per_s"] / results["plain_f64"]["matvec_per_s"]
     if "batched_f64" in outputs:
