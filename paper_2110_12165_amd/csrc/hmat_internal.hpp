@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <atomic>
 #include <cstdint>
+#include <exception>
+#include <mutex>
 #include <new>
 #include <sched.h>
 #include <stdexcept>
@@ -58,19 +60,37 @@ inline int32_t host_threads() {
 }
 
 // Runs f(0 .. count-1) on up to n_threads threads (0: host_threads()),
-// items handed out one at a time.  f must not throw.
+// items handed out one at a time.  If f throws, the remaining items are
+// skipped and the first exception is rethrown after all threads joined.
 template <typename F>
 void parallel_for(int64_t count, int32_t n_threads, F&& f) {
   int64_t nt = n_threads > 0 ? n_threads : host_threads();
   nt = std::max<int64_t>(1, std::min<int64_t>(nt, count));
   std::atomic<int64_t> next{0};
+  std::atomic<bool> failed{false};
+  std::exception_ptr err;
+  std::mutex err_mu;
   auto work = [&] {
-    for (int64_t k; (k = next.fetch_add(1)) < count;) f(k);
+    try {
+      for (int64_t k; !failed.load(std::memory_order_relaxed) && (k = next.fetch_add(1)) < count;) f(k);
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(err_mu);
+      if (!err) err = std::current_exception();
+      failed.store(true);
+    }
   };
   std::vector<std::thread> th;
-  for (int64_t t = 1; t < nt; ++t) th.emplace_back(work);
+  th.reserve((size_t)nt);
+  try {
+    for (int64_t t = 1; t < nt; ++t) th.emplace_back(work);
+  } catch (...) {  // no more threads: stop the started ones and report
+    failed.store(true);
+    for (auto& t : th) t.join();
+    throw;
+  }
   work();
   for (auto& t : th) t.join();
+  if (err) std::rethrow_exception(err);
 }
 
 // Sets v[0 .. size) to zero in chunks spread over threads.
