@@ -783,11 +783,12 @@ void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* 
   for (int stage = 0; stage < 6; ++stage) {
     const double* yin = y;
     if (stage > 0) {
-      check_hip(hm::launch_rk_stage(n3, stage, w.st, y, w.k, w.ys, s), "stage launch");
+      check_hip(hm::launch_rk_stage_slip(n, stage, w.st, 0.0, y, w.k, w.ys, p->V0, p->V_pl, p->a, w.xv, s),
+                "stage launch");
       yin = w.ys;
+    } else {
+      check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, y, w.xv, w.Vs, s), "slip-rate launch");
     }
-    check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, yin, w.xv, stage == 0 ? w.Vs : nullptr, s),
-              "slip-rate launch");
     check_hip(A->product(false, w.xv, w.ax, 1.0, 0.0, s, A->kernel), "product launch");
     if (B) check_hip(B->product(false, w.xv, w.bx, 1.0, 0.0, s, B->kernel), "product launch");
     check_hip(hm::launch_rs_rhs(n, *p, yin, w.ax, B ? w.bx : nullptr, w.k + stage * n3, s), "rhs launch");
@@ -908,10 +909,12 @@ void enqueue_frozen_step(hmat_t A, hmat_t B, const rs_params* p, const double* y
     const double* yin = y_in;
     if (stage > 0) {
       double* dst = Ystore ? Ystore + (stage - 1) * n3 : ys;
-      check_hip(hm::launch_rk_stage_dt(n3, stage, dt, y_in, K, dst, s), "stage launch");
+      check_hip(hm::launch_rk_stage_slip(n, stage, nullptr, dt, y_in, K, dst, p->V0, p->V_pl, p->a, x, s),
+                "stage launch");
       yin = dst;
+    } else {
+      check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, y_in, x, nullptr, s), "slip-rate launch");
     }
-    check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, yin, x, nullptr, s), "slip-rate launch");
     check_hip(A->product(false, x, ax, 1.0, 0.0, s, A->kernel), "product launch");
     if (B) check_hip(B->product(false, x, bx, 1.0, 0.0, s, B->kernel), "product launch");
     check_hip(hm::launch_rs_rhs(n, *p, yin, ax, B ? bx : nullptr, K + stage * n3, s), "rhs launch");
@@ -1051,11 +1054,12 @@ void enqueue_ens_attempt(hmat_t A, hmat_t B, const rs_ens_params* p, double* y, 
   for (int stage = 0; stage < 6; ++stage) {
     const double* yin = y;
     if (stage > 0) {
-      check_hip(hm::launch_ens_stage(n3, M, stage, w.st, y, w.k, w.ys, s), "ensemble stage launch");
+      check_hip(hm::launch_ens_stage_slip(n, M, stage, w.st, y, w.k, w.ys, p->V0, p->V_pl, p->a, w.x, s),
+                "ensemble stage launch");
       yin = w.ys;
+    } else {
+      check_hip(hm::launch_ens_slip(n, M, p->V0, p->V_pl, p->a, y, w.x, w.Vs, s), "ensemble slip-rate launch");
     }
-    check_hip(hm::launch_ens_slip(n, M, p->V0, p->V_pl, p->a, yin, w.x, stage == 0 ? w.Vs : nullptr, s),
-              "ensemble slip-rate launch");
     enqueue_mm(A, w.x, M, w.ax, M, M, 1.0, 0.0, p->mode, s);
     if (B) enqueue_mm(B, w.x, M, w.bx, M, M, 1.0, 0.0, p->mode, s);
     check_hip(hm::launch_ens_rhs(n, M, p->V0, p->f0, p->eta_rad, p->a, p->b, p->dc, yin, w.ax, B ? w.bx : nullptr,

@@ -63,18 +63,33 @@ __global__ void k_rhs(int64_t n, double V0, double f0, double eta, const double*
 // relative difference of the two solutions (section 2.2) and the accepted
 // update with the trapezoidal slip rule of eq. (16).
 // ---------------------------------------------------------------------------
-// ys = y + dt * sum_{j<s} a_sj k_j
-__global__ void k_stage(int64_t n3, int s, const RkDevState* __restrict__ st, const double* __restrict__ y,
-                        const double* __restrict__ k, double* __restrict__ ys) {
+// Stage input ys = y + dt * sum_{j<s} a_sj k_j (the three components of
+// element i) and the product input x_i = V(ys_i) - V_pl, in one pass.  The
+// step comes from the device state st or, when st is null, from dt.
+__global__ void k_stage_slip(int64_t n, int s, const RkDevState* __restrict__ st, double dt_val,
+                             const double* __restrict__ y, const double* __restrict__ k, double* __restrict__ ys,
+                             double V0, double V_pl, const double* __restrict__ a, double* __restrict__ x) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n3) return;
-  const double dt = st->dt;
-  double v = y[i];
-  for (int j = 0; j < s; ++j) {
-    const double c = kA[s][j];
-    if (c != 0.0) v = v + (dt * c) * k[j * n3 + i];
+  if (i >= n) return;
+  const int64_t n3 = 3 * n;
+  const double dt = st ? st->dt : dt_val;
+  double v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t e = c * n + i;
+    double w = y[e];
+    for (int j = 0; j < s; ++j) {
+      const double cf = kA[s][j];
+      if (cf != 0.0) w = w + (dt * cf) * k[j * n3 + e];
+    }
+    ys[e] = w;
+    v[c] = w;
   }
-  ys[i] = v;
+  const double ai = a[i];
+  const double q = v[1] / (ai * v[2]);
+  const double ee = v[0] / ai;
+  const double V = V0 * (exp(q - ee) - exp(-q - ee));
+  x[i] = V - V_pl;
 }
 
 __global__ void k_begin(RkDevState* st) { st->err_bits = 0ull; }
@@ -163,10 +178,12 @@ __global__ void k_accept(int64_t n, const RkDevState* __restrict__ st, double V0
 
 }  // namespace
 
-hipError_t launch_rk_stage(int64_t n3, int s, const RkDevState* st, const double* y, const double* k, double* ys,
-                           hipStream_t strm) {
+hipError_t launch_rk_stage_slip(int64_t n, int s, const RkDevState* st, double dt, const double* y, const double* k,
+                                double* ys, double V0, double V_pl, const double* a, double* x, hipStream_t strm) {
+  if (s < 1 || s > 5) return hipErrorInvalidValue;
   const int bs = 256;
-  hipLaunchKernelGGL(k_stage, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, strm, n3, s, st, y, k, ys);
+  hipLaunchKernelGGL(k_stage_slip, dim3((unsigned)((n + bs - 1) / bs)), dim3(bs), 0, strm, n, s, st, dt, y, k, ys, V0,
+                     V_pl, a, x);
   return hipGetLastError();
 }
 

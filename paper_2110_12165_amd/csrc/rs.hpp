@@ -18,14 +18,17 @@ hipError_t launch_rs_slip_rate(int64_t n, double V0, double V_pl, const double* 
 hipError_t launch_rs_rhs(int64_t n, const rs_params& p, const double* y, const double* ax, const double* bx,
                          double* dydt, hipStream_t s);
 
-// One Runge-Kutta attempt is: launch_rk_begin, six stages (launch_rk_stage
-// for stages 1..5, then slip rate, products and right-hand side), then
-// launch_rk_finish_control and launch_rk_accept.  All read the step from the
-// device state, so the sequence can be captured in a graph.
+// One Runge-Kutta attempt is: launch_rk_begin, six stages (the slip rate of
+// y for stage 0, launch_rk_stage_slip for stages 1..5; then the products and
+// the right-hand side), then launch_rk_finish_control and launch_rk_accept.
+// All read the step from the device state, so the sequence can be captured
+// in a graph.
 hipError_t launch_rk_begin(RkDevState* st, hipStream_t strm);
-// Cash-Karp stage input ys = y + dt sum_{j<s} a_sj k_j (k: 6 blocks of n3).
-hipError_t launch_rk_stage(int64_t n3, int s, const RkDevState* st, const double* y, const double* k, double* ys,
-                           hipStream_t strm);
+// Cash-Karp stage input ys = y + dt sum_{j<s} a_sj k_j (k: 6 blocks of 3n,
+// s in 1..5) and x = V(ys) - V_pl (eq. (7)).  dt is read from st, or taken
+// from the argument when st is null (frozen steps).
+hipError_t launch_rk_stage_slip(int64_t n, int s, const RkDevState* st, double dt, const double* y, const double* k,
+                                double* ys, double V0, double V_pl, const double* a, double* x, hipStream_t strm);
 // y5, the largest relative difference |y5 - y4| / |y5| and the step control.
 hipError_t launch_rk_finish_control(int64_t n3, RkDevState* st, const double* y, const double* k, double* y5,
                                     hipStream_t strm);

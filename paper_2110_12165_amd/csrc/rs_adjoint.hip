@@ -27,19 +27,6 @@ constexpr int kBs = 256;
 
 inline unsigned blocks(int64_t n) { return (unsigned)((n + kBs - 1) / kBs); }
 
-// ys = y + dt * sum_{j<s} a_sj k_j, the step given as a value
-__global__ void k_stage_dt(int64_t n3, int s, double dt, const double* __restrict__ y, const double* __restrict__ k,
-                           double* __restrict__ ys) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n3) return;
-  double v = y[i];
-  for (int j = 0; j < s; ++j) {
-    const double c = kA[s][j];
-    if (c != 0.0) v = v + (dt * c) * k[j * n3 + i];
-  }
-  ys[i] = v;
-}
-
 __device__ __forceinline__ double slip_rate(double phi, double tau, double sig, double a, double V0) {
   const double q = tau / (a * sig), e = phi / a;
   return V0 * (exp(q - e) - exp(-q - e));
@@ -201,12 +188,6 @@ __global__ void k_combine(int64_t n3, double* __restrict__ ybar, const double* _
 }
 
 }  // namespace
-
-hipError_t launch_rk_stage_dt(int64_t n3, int s, double dt, const double* y, const double* k, double* ys,
-                              hipStream_t strm) {
-  hipLaunchKernelGGL(k_stage_dt, dim3(blocks(n3)), dim3(kBs), 0, strm, n3, s, dt, y, k, ys);
-  return hipGetLastError();
-}
 
 hipError_t launch_rk_update_dt(int64_t n, double dt, double V0, const double* a, const double* k, const double* y,
                                double* y_out, double* D, hipStream_t strm) {

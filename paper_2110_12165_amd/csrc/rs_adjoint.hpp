@@ -9,9 +9,6 @@
 
 namespace hm {
 
-// Cash-Karp stage input ys = y + dt sum_{j<s} a_sj k_j (k: 6 blocks of n3).
-hipError_t launch_rk_stage_dt(int64_t n3, int s, double dt, const double* y, const double* k, double* ys,
-                              hipStream_t strm);
 // y_out = y + dt sum_j b5_j k_j and D += dt/2 (V(y) + V(y_out)) (eq. (16);
 // D may be null); y_out may alias y.
 hipError_t launch_rk_update_dt(int64_t n, double dt, double V0, const double* a, const double* k, const double* y,

@@ -33,20 +33,29 @@ __global__ void k_ens_begin(EnsDevState* st) {
   if (threadIdx.x < kEnsMax) st->err_bits[threadIdx.x] = 0ull;
 }
 
-// ys = y + dt_r sum_{j<s} a_sj k_j
-__global__ void k_ens_stage(int64_t n3, int M, int s, const EnsDevState* __restrict__ st, const double* __restrict__ y,
-                            const double* __restrict__ k, double* __restrict__ ys) {
-  int64_t e;
+// Stage input ys = y + dt_r sum_{j<s} a_sj k_j (the three components of
+// element i, member r) and the product input x = V(ys) - V_pl, in one pass.
+__global__ void k_ens_stage_slip(int64_t n, int M, int s, const EnsDevState* __restrict__ st,
+                                 const double* __restrict__ y, const double* __restrict__ k, double* __restrict__ ys,
+                                 double V0, double V_pl, const double* __restrict__ a, double* __restrict__ x) {
+  int64_t i;
   int r;
-  if (!elem(n3, M, e, r)) return;
-  const int64_t idx = e * M + r, stride = n3 * M;
+  if (!elem(n, M, i, r)) return;
+  const int64_t nm = n * M, stride = 3 * nm;
   const double dt = st->dt[r];
-  double v = y[idx];
-  for (int j = 0; j < s; ++j) {
-    const double c = kA[s][j];
-    if (c != 0.0) v = v + (dt * c) * k[j * stride + idx];
+  double v[3];
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const int64_t idx = c * nm + i * M + r;
+    double w = y[idx];
+    for (int j = 0; j < s; ++j) {
+      const double cf = kA[s][j];
+      if (cf != 0.0) w = w + (dt * cf) * k[j * stride + idx];
+    }
+    ys[idx] = w;
+    v[c] = w;
   }
-  ys[idx] = v;
+  x[i * M + r] = slip_rate(v[0], v[1], v[2], a[i * M + r], V0) - V_pl;
 }
 
 // x = V(y) - V_pl (eq. (7)); V_out (or null) receives V
@@ -171,9 +180,11 @@ hipError_t launch_ens_begin(EnsDevState* st, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_ens_stage(int64_t n3, int M, int stage, const EnsDevState* st, const double* y, const double* k,
-                            double* ys, hipStream_t s) {
-  hipLaunchKernelGGL(k_ens_stage, grid_for(n3), dim3(kEnsMax, 4), 0, s, n3, M, stage, st, y, k, ys);
+hipError_t launch_ens_stage_slip(int64_t n, int M, int stage, const EnsDevState* st, const double* y, const double* k,
+                                 double* ys, double V0, double V_pl, const double* a, double* x, hipStream_t s) {
+  if (stage < 1 || stage > 5) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ens_stage_slip, grid_for(n), dim3(kEnsMax, 4), 0, s, n, M, stage, st, y, k, ys, V0, V_pl, a,
+                     x);
   return hipGetLastError();
 }
 
