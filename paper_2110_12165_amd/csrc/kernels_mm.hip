@@ -29,7 +29,12 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kNR = 64;       // members per product (N)
-constexpr int kKS = 64;       // inputs staged per round (K)
+// Inputs staged per round (K).  Measured at N = 122880: BF16x6 runs faster
+// with rounds of 32 (0.640 against 0.683 ms: its 3-part LDS rows then need
+// 12 KB, not 24, and more workgroups fit), BF16x3 with rounds of 64 (0.450
+// against 0.510 ms).
+template <int NS>
+constexpr int ks_of() { return NS == 3 ? 32 : 64; }
 constexpr int kWaves = 4;
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
@@ -87,7 +92,9 @@ __global__ __launch_bounds__(256) void k_split_members(int64_t n, int nrhs, cons
   for (int i = 0; i < NS; ++i) Xs[((int64_t)i * n + k) * kNR + r] = p[i];
 }
 
-constexpr int kItems = kKS * 8 / (kWaves * 64);  // 16-byte staging items per thread and part
+// 16-byte staging items per thread and part
+template <int NS>
+constexpr int items_of() { return ks_of<NS>() * 8 / (kWaves * 64); }
 
 // Workgroups are dealt to the 8 XCDs round-robin in dispatch order, and each
 // XCD has its own L2.  The 64-output slices of one phase-1 unit stage the
@@ -107,16 +114,16 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
   return ((rest / kChunk) * kXcds + xcd) * kChunk + rest % kChunk;
 }
 
-// Members of inputs c0 + [0, kKS) of a unit, split parts, read into registers
+// Members of inputs c0 + [0, K_S) of a unit, split parts, read into registers
 // (item e = tid + 256 i: input e / 8, 8-member chunk e % 8); zero beyond the
 // unit's inputs and for the zero pad of the intermediate vector.
 template <int NS, int PHASE>
 __device__ __forceinline__ void stage_load(const MMArgs& a, const Unit& u, int c0, int K, int tid,
-                                           s16x8 (&sr)[NS][kItems]) {
+                                           s16x8 (&sr)[NS][items_of<NS>()]) {
   const __bf16* __restrict__ Xs = static_cast<const __bf16*>(a.Xs);
   const __bf16* Ts = static_cast<const __bf16*>(a.Ts);
 #pragma unroll
-  for (int it = 0; it < kItems; ++it) {
+  for (int it = 0; it < items_of<NS>(); ++it) {
     const int e = tid + it * kWaves * 64;
     const int ch = e & 7, k = c0 + (e >> 3);
     const __bf16* row = nullptr;
@@ -145,9 +152,10 @@ __device__ __forceinline__ void stage_load(const MMArgs& a, const Unit& u, int c
 }
 
 template <int NS>
-__device__ __forceinline__ void stage_store(unsigned short (*zs)[kKS][kNR], int tid, const s16x8 (&sr)[NS][kItems]) {
+__device__ __forceinline__ void stage_store(unsigned short (*zs)[ks_of<NS>()][kNR], int tid,
+                                            const s16x8 (&sr)[NS][items_of<NS>()]) {
 #pragma unroll
-  for (int it = 0; it < kItems; ++it) {
+  for (int it = 0; it < items_of<NS>(); ++it) {
     const int e = tid + it * kWaves * 64;
     const int ch = e & 7, kk = e >> 3;
 #pragma unroll
@@ -155,12 +163,13 @@ __device__ __forceinline__ void stage_store(unsigned short (*zs)[kKS][kNR], int 
   }
 }
 
-// Panel quads of output o for the four 32-input steps of the round at c0:
+// Panel quads of output o for the NST 32-input steps of the round at c0:
 // step s, half h = quad (c0 + 32 s) / 4 + 2 lk + h.
+template <int NST>
 __device__ __forceinline__ void load_a(const float* pool, const Unit& u, int c0, int o, bool orow, int lk,
-                                       f32x4 (&ar)[kKS / 32][2]) {
+                                       f32x4 (&ar)[NST][2]) {
 #pragma unroll
-  for (int st = 0; st < kKS / 32; ++st)
+  for (int st = 0; st < NST; ++st)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int q = (c0 + 32 * st) / 4 + 2 * lk + h;
@@ -181,7 +190,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
   __bf16* Ts = static_cast<__bf16*>(a.Ts);
   // bf16 bit patterns as 16-bit integers (whole vectors are bit-cast to bf16);
   // row = input of the round, 64 members, chunks swizzled by zchunk
-  __shared__ __attribute__((aligned(16))) unsigned short zs[NS][kKS][kNR];
+  constexpr int KS = ks_of<NS>();
+  __shared__ __attribute__((aligned(16))) unsigned short zs[NS][KS][kNR];
   int ui, ob = 0;
   if (PHASE == 1) {
     const int code = a.slices1[xcd_remap((int)blockIdx.x, (int)gridDim.x)];
@@ -196,14 +206,14 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
   const int lm = lane & 15, lk = lane >> 4;  // MFMA lane: row/col within 16, k group of 8
   const int ntiles = (min(u.nout, ob + 64) - ob + 15) >> 4;
   const int K = u.nq * 4;
-  const int rounds = (K + kKS - 1) / kKS;
+  const int rounds = (K + KS - 1) / KS;
   const int o = ob + wave * 16 + lm;
   const bool work = wave < ntiles, orow = work && o < u.nout;
   f32x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  s16x8 sr[NS][kItems];
-  f32x4 ar[kKS / 32][2], an[kKS / 32][2];
+  s16x8 sr[NS][items_of<NS>()];
+  f32x4 ar[KS / 32][2], an[KS / 32][2];
   stage_load<NS, PHASE>(a, u, 0, K, tid, sr);
   if (work) load_a(pool, u, 0, o, orow, lk, ar);
   stage_store<NS>(zs, tid, sr);
@@ -212,12 +222,12 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
   for (int r = 0; r < rounds; ++r) {
     const bool more = r + 1 < rounds;
     if (more) {
-      stage_load<NS, PHASE>(a, u, (r + 1) * kKS, K, tid, sr);
-      if (work) load_a(pool, u, (r + 1) * kKS, o, orow, lk, an);
+      stage_load<NS, PHASE>(a, u, (r + 1) * KS, K, tid, sr);
+      if (work) load_a(pool, u, (r + 1) * KS, o, orow, lk, an);
     }
     if (work) {
 #pragma unroll
-      for (int st = 0; st < kKS / 32; ++st) {
+      for (int st = 0; st < KS / 32; ++st) {
         // A fragment: output o, inputs 32 st + 8 lk + [0, 8) of the round
         bf16x8 ap[NS];
 #pragma unroll
@@ -247,7 +257,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
     if (more) {
       stage_store<NS>(zs, tid, sr);
 #pragma unroll
-      for (int st = 0; st < kKS / 32; ++st) {
+      for (int st = 0; st < KS / 32; ++st) {
         ar[st][0] = an[st][0];
         ar[st][1] = an[st][1];
       }
