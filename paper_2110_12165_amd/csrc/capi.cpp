@@ -553,6 +553,7 @@ void enqueue_mm(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, 
   a.n2 = h->batched.n2;
   a.slices1 = h->mm_slices1;
   a.ns1 = h->mm_ns1;
+  a.cus = h->cus;
   a.src = h->batched.src;
   a.pool = h->batched.pool;
   a.perm = h->d_perm;

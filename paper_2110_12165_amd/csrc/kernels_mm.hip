@@ -29,12 +29,13 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef short s16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kNR = 64;       // members per product (N)
-// Inputs staged per round (K).  Measured at N = 122880: BF16x6 runs faster
-// with rounds of 32 (0.640 against 0.683 ms: its 3-part LDS rows then need
-// 12 KB, not 24, and more workgroups fit), BF16x3 with rounds of 64 (0.450
-// against 0.510 ms).
-template <int NS>
-constexpr int ks_of() { return NS == 3 ? 32 : 64; }
+// Inputs staged per round (KS, 32 or 64, a template argument of the kernel).
+// Measured (per phase, N = 122880 / 21000): BF16x3 runs faster with rounds
+// of 64 in both phases; BF16x6 phase 2 with rounds of 32 (340 against 367 us
+// / 101 against 125 us: its 3-part LDS rows then need 12 KB, not 24, and
+// more workgroups fit), BF16x6 phase 1 with 32 when it has many slices
+// (N = 122880: 260 against 281 us) and with 64 when it has few (N = 21000:
+// 90 against 108 us).
 constexpr int kWaves = 4;
 
 typedef short s16x4 __attribute__((ext_vector_type(4)));
@@ -93,8 +94,8 @@ __global__ __launch_bounds__(256) void k_split_members(int64_t n, int nrhs, cons
 }
 
 // 16-byte staging items per thread and part
-template <int NS>
-constexpr int items_of() { return ks_of<NS>() * 8 / (kWaves * 64); }
+template <int KS>
+constexpr int items_of() { return KS * 8 / (kWaves * 64); }
 
 // Workgroups are dealt to the 8 XCDs round-robin in dispatch order, and each
 // XCD has its own L2.  The 64-output slices of one phase-1 unit stage the
@@ -117,13 +118,13 @@ __device__ __forceinline__ int xcd_remap(int b, int G) {
 // Members of inputs c0 + [0, K_S) of a unit, split parts, read into registers
 // (item e = tid + 256 i: input e / 8, 8-member chunk e % 8); zero beyond the
 // unit's inputs and for the zero pad of the intermediate vector.
-template <int NS, int PHASE>
+template <int NS, int PHASE, int KS>
 __device__ __forceinline__ void stage_load(const MMArgs& a, const Unit& u, int c0, int K, int tid,
-                                           s16x8 (&sr)[NS][items_of<NS>()]) {
+                                           s16x8 (&sr)[NS][items_of<KS>()]) {
   const __bf16* __restrict__ Xs = static_cast<const __bf16*>(a.Xs);
   const __bf16* Ts = static_cast<const __bf16*>(a.Ts);
 #pragma unroll
-  for (int it = 0; it < items_of<NS>(); ++it) {
+  for (int it = 0; it < items_of<KS>(); ++it) {
     const int e = tid + it * kWaves * 64;
     const int ch = e & 7, k = c0 + (e >> 3);
     const __bf16* row = nullptr;
@@ -151,11 +152,11 @@ __device__ __forceinline__ void stage_load(const MMArgs& a, const Unit& u, int c
   }
 }
 
-template <int NS>
-__device__ __forceinline__ void stage_store(unsigned short (*zs)[ks_of<NS>()][kNR], int tid,
-                                            const s16x8 (&sr)[NS][items_of<NS>()]) {
+template <int NS, int KS>
+__device__ __forceinline__ void stage_store(unsigned short (*zs)[KS][kNR], int tid,
+                                            const s16x8 (&sr)[NS][items_of<KS>()]) {
 #pragma unroll
-  for (int it = 0; it < items_of<NS>(); ++it) {
+  for (int it = 0; it < items_of<KS>(); ++it) {
     const int e = tid + it * kWaves * 64;
     const int ch = e & 7, kk = e >> 3;
 #pragma unroll
@@ -185,12 +186,11 @@ __device__ __forceinline__ void load_a(const float* pool, const Unit& u, int c0,
 // software-pipelined: the members and panel quads of the next round are
 // loaded into registers while the MFMAs of the current round run, and
 // written to LDS after it.
-template <int NS, int PHASE>
+template <int NS, int PHASE, int KS>
 __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, double beta) {
   __bf16* Ts = static_cast<__bf16*>(a.Ts);
   // bf16 bit patterns as 16-bit integers (whole vectors are bit-cast to bf16);
   // row = input of the round, 64 members, chunks swizzled by zchunk
-  constexpr int KS = ks_of<NS>();
   __shared__ __attribute__((aligned(16))) unsigned short zs[NS][KS][kNR];
   int ui, ob = 0;
   if (PHASE == 1) {
@@ -212,17 +212,17 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
   f32x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  s16x8 sr[NS][items_of<NS>()];
+  s16x8 sr[NS][items_of<KS>()];
   f32x4 ar[KS / 32][2], an[KS / 32][2];
-  stage_load<NS, PHASE>(a, u, 0, K, tid, sr);
+  stage_load<NS, PHASE, KS>(a, u, 0, K, tid, sr);
   if (work) load_a(pool, u, 0, o, orow, lk, ar);
-  stage_store<NS>(zs, tid, sr);
+  stage_store<NS, KS>(zs, tid, sr);
   __syncthreads();
 
   for (int r = 0; r < rounds; ++r) {
     const bool more = r + 1 < rounds;
     if (more) {
-      stage_load<NS, PHASE>(a, u, (r + 1) * KS, K, tid, sr);
+      stage_load<NS, PHASE, KS>(a, u, (r + 1) * KS, K, tid, sr);
       if (work) load_a(pool, u, (r + 1) * KS, o, orow, lk, an);
     }
     if (work) {
@@ -255,7 +255,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
     }
     __syncthreads();
     if (more) {
-      stage_store<NS>(zs, tid, sr);
+      stage_store<NS, KS>(zs, tid, sr);
 #pragma unroll
       for (int st = 0; st < KS / 32; ++st) {
         ar[st][0] = an[st][0];
@@ -288,15 +288,22 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
   }
 }
 
+constexpr int kManySlices = 16;  // phase-1 slices per compute unit from which BF16x6 stages 32 inputs
+
 template <int NS>
 hipError_t launch_ns(const MMArgs& a, double alpha, double beta, hipStream_t s, hipEvent_t* ev) {
   const int64_t n = a.n;
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_split_members<NS>), dim3((unsigned)((n * kNR + 255) / 256)), dim3(256), 0, s, n, a.nrhs, a.X,
                      a.ldx, a.perm, static_cast<__bf16*>(a.Xs));
-  if (a.ns1 > 0) hipLaunchKernelGGL((k_mm<NS, 1>), dim3(a.ns1), dim3(kWaves * 64), 0, s, a, alpha, beta);
+  if (a.ns1 > 0) {
+    if (NS == 3 && a.ns1 >= kManySlices * a.cus)
+      hipLaunchKernelGGL((k_mm<NS, 1, 32>), dim3(a.ns1), dim3(kWaves * 64), 0, s, a, alpha, beta);
+    else
+      hipLaunchKernelGGL((k_mm<NS, 1, 64>), dim3(a.ns1), dim3(kWaves * 64), 0, s, a, alpha, beta);
+  }
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (a.n2 > 0) hipLaunchKernelGGL((k_mm<NS, 2>), dim3(a.n2), dim3(kWaves * 64), 0, s, a, alpha, beta);
+  if (a.n2 > 0) hipLaunchKernelGGL((k_mm<NS, 2, NS == 3 ? 32 : 64>), dim3(a.n2), dim3(kWaves * 64), 0, s, a, alpha, beta);
   if (ev) (void)hipEventRecord(ev[2], s);
   return hipGetLastError();
 }

@@ -24,6 +24,7 @@ struct MMArgs {
   double* Y;               // user order, element-major: Y[i * ldy + r]
   int64_t ldy;
   int32_t nrhs;            // 1..64
+  int32_t cus;             // compute units of the device
 };
 
 // parts = 2 (3 bf16 products, "BF16x3") or 3 (6 products, "BF16x6").
