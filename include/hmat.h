@@ -116,7 +116,7 @@ typedef struct {
   int32_t wg_waves_p1;     /* BATCHED split: waves per workgroup of phase 1 (4, 8, 16);
                               0 = default (4) */
   int32_t max_nrhs;        /* > 0: allocate the buffers of hmat_matmat at creation (needs
-                              HMAT_F32, a BATCHED kernel and wg_waves_p1 <= 4); 0: none */
+                              HMAT_F32 and a BATCHED kernel); 0: none */
   int32_t transpose;       /* 1: also lay out H^T for hmat_matvec_T (doubles the factor
                               storage); 0: hmat_matvec_T returns HMAT_ESTATE */
   int32_t build_device;    /* hmat_build: 1 = evaluate entries and run ACA on the GPU (same
@@ -184,8 +184,9 @@ typedef struct {
  * hmat_build — construct the lattice H-matrix of one stiffness matrix.
  * Section 3.1.1 (cluster tree on element centres, eq. (17) admissibility),
  * section 3.2 (lattice: tree cut at depth log2(lattice), each lattice block
- * partitioned on its own), section 3.1.2 (ACA, eqs. (18)-(19), FP64 on host
- * threads), then packing and upload of the factors to the current device.
+ * partitioned on its own), section 3.1.2 (ACA, eqs. (18)-(19), FP64, on host
+ * threads or, with opts.build_device, on the current device), then packing
+ * and upload of the factors to the current device.
  *   mesh, green, opts: host structs, validated (EINVAL on any bad field,
  *     non-finite coordinate, non-planar or non-rectangular element for the
  *     coplanar kernel, lattice not a power of two or deeper than the tree).
@@ -235,7 +236,10 @@ hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int6
 
 /* hmat_matvec_T — y = alpha * H^T x + beta * y; same arguments and rules.
  * Runs the product kernels on the packed blocks of H^T (dense blocks
- * transposed, U and V exchanged); needs a handle created with transpose = 1. */
+ * transposed, U and V exchanged); needs a handle created with transpose = 1
+ * (HMAT_ESTATE otherwise).  The backward of the product y = H x. */
+hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld,
+                          double alpha, double beta, void* stream);
 
 /*
  * hmat_matmat — Y = alpha * H X + beta * Y for nrhs members at once
@@ -251,8 +255,6 @@ hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int6
  */
 hmat_status hmat_matmat(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrhs, double alpha,
                         double beta, int32_t mode, void* stream);
-hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld,
-                          double alpha, double beta, void* stream);
 
 /* hmat_info — statistics of the handle (host struct filled, no GPU work). */
 hmat_status hmat_info(hmat_t h, hmat_stats* out);
