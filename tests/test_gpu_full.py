@@ -59,3 +59,34 @@ def test_full_size_against_exact_product(setup, variant):
     ref = dense_rows(g, rows, x)
     assert np.max(np.abs(y1[rows] - ref)) <= 1e-5 * np.max(np.abs(y_exact))
     assert info["max_rank"] <= 64 and info["n_lr"] > 40000
+
+
+def test_aca_tolerance_controls_the_product_error():
+    """The ACA tolerance of eq. (19) sets the product's error: at N = 30720
+    (the benchmark fault at a quarter of its size) and eps from 1e-3 to
+    1e-8, the FP64 product (matrix built on the device) stays within 3 eps
+    of the exact product, the error falls with eps and the stored entries
+    grow — the one-GPU analogue of the paper's tolerance study."""
+    import torch
+
+    import paper_2110_12165_amd as hm
+    name = "dip30_240x128"
+    w = WORKLOADS[name]
+    f = config_fault(name)
+    x = loguniform_rates(f.n, w["seed"])
+    y_exact = fft_grid_product(f.nx, f.ny, f.h, f.slip, MU, NU, x)
+    xd = torch.tensor(x, device="cuda:0")
+    errs, stored = [], []
+    for eps in (1e-3, 1e-4, 1e-5, 1e-6, 1e-7, 1e-8):
+        H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=eps, eta=w["eta"], leaf=w["leaf"],
+                             lattice=w["lattice"], prec="f64", kernel="split", build_device=1, transpose=0)
+        y = H.matvec(xd).cpu().numpy()
+        info = H.info()
+        H.close()
+        errs.append(rel(y, y_exact))
+        stored.append((info["dense_entries"] + info["lr_entries"]) / float(f.n) ** 2)
+        say(f"[eps] {name} N={f.n} eps {eps:.0e}: rel error {errs[-1]:.2e}, stored {100 * stored[-1]:.2f} %, "
+            f"max rank {info['max_rank']}")
+        assert errs[-1] <= 3 * eps
+    assert all(b < a for a, b in zip(errs, errs[1:]))
+    assert all(b > a for a, b in zip(stored, stored[1:]))
