@@ -620,8 +620,8 @@ def main():
                     help="also run one device copy of this many MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: the product is not sharded across GPUs in this build "
-              "(see the multi-GPU design notes); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the product is not sharded across GPUs "
+              "(the sharding is described with the design notes); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

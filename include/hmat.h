@@ -50,7 +50,7 @@ typedef enum {
   HMAT_ENOMEM = -2,       /* host or device allocation failed */
   HMAT_EDEVICE = -3,      /* a HIP runtime call failed (message names it) */
   HMAT_ESTATE = -4,       /* handle in an unusable state */
-  HMAT_EUNSUPPORTED = -5  /* valid request this build does not implement */
+  HMAT_EUNSUPPORTED = -5  /* valid request the library does not implement */
 } hmat_status;
 
 /* Storage precision of the factors on the device.  Products always take and

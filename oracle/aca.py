@@ -7,7 +7,7 @@ The rank grows until the newest rank-one term is small against the
 running Frobenius-norm estimate of the approximation (the paper notes that
 eq. 19 cannot be checked exactly because the full block is never formed).
 
-Steps as implemented (this build's reading; the paper does not spell out
+Steps as implemented (a reading of the method; the paper does not spell out
 the variant, the first pivot, ties or the rank-control method it cites):
 
 1. Start from the first row of the block; no row used yet; S2 = 0.
