@@ -206,12 +206,14 @@ struct hmat_s {
   // Batched layout of H^T, kept for the life of the handle (fixed set).
   template <typename T>
   void setup_batched_t(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
-    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1, true, opts.n_threads);
+    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1, true, opts.n_threads, split_slots<T>(wg1));
     batched_t.units = upload(L.units, s);
     batched_t.n1 = L.n1;
     batched_t.n2 = L.n2;
     batched_t.src = upload(L.src, s);
     batched_t.t = alloc_zero<double>((size_t)L.t_size, s);
+    batched_t.sums = L.sums.empty() ? nullptr : upload(L.sums, s);
+    batched_t.t_size = (int32_t)L.t_size;
     batched_t.pool = upload(L.pool, s);
     batched_t.perm = d_perm;
     batched_t.ctr = alloc_zero<hm::QueueCounters>(1, s);
@@ -222,14 +224,49 @@ struct hmat_s {
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
   }
 
+  // Row splitting of oversized phase-1 units (make_batched's split_slots):
+  // -1 where phase 1 has few units per resident workgroup, 0 never, 1
+  // wherever a unit is far above the mean.  Never for handles with ensemble
+  // buffers: the ensemble product stages intermediate values split into bf16
+  // parts and cannot add partial ones.
+  int32_t split_mode = -1;
+  template <typename T>
+  int64_t split_slots(int32_t wg1) const {
+    if (opts.max_nrhs > 0 || split_mode == 0) return 0;
+    if (split_mode == 1) return INT32_MAX;
+    return (int64_t)hm::phase1_blocks_per_cu<T>(wg1) * cus;
+  }
+
+  // Mean duration of `reps` products (after two untimed ones) on stream s.
+  double time_product(hipStream_t s, int reps) {
+    struct Ev {
+      hipEvent_t e = nullptr;
+      Ev() { check_hip(hipEventCreate(&e), "hipEventCreate"); }
+      ~Ev() { (void)hipEventDestroy(e); }
+    } e0, e1;
+    for (int w = 0; w < 2; ++w) check_hip(product(false, rs_x, rs_ax, 1.0, 0.0, s, kernel), "product launch");
+    check_hip(hipEventRecord(e0.e, s), "hipEventRecord");
+    for (int r = 0; r < reps; ++r) check_hip(product(false, rs_x, rs_ax, 1.0, 0.0, s, kernel), "product launch");
+    check_hip(hipEventRecord(e1.e, s), "hipEventRecord");
+    check_hip(hipEventSynchronize(e1.e), "hipEventSynchronize");
+    float ms = 0.f;
+    check_hip(hipEventElapsedTime(&ms, e0.e, e1.e), "hipEventElapsedTime");
+    return (double)ms / reps;
+  }
+
   template <typename T>
   void setup_batched(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
-    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1, false, opts.n_threads);
+    // Row-split phase-1 units write partial intermediate values that the
+    // ensemble product cannot add (it stages them split into bf16 parts):
+    // handles with ensemble buffers keep whole units.
+    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1, false, opts.n_threads, split_slots<T>(wg1));
     batched.units = upload(L.units, s, true);
     batched.n1 = L.n1;
     batched.n2 = L.n2;
     batched.src = upload(L.src, s, true);
     batched.t = alloc_zero<double>((size_t)L.t_size, s, true);
+    batched.sums = L.sums.empty() ? nullptr : upload(L.sums, s, true);
+    batched.t_size = (int32_t)L.t_size;
     batched.pool = upload(L.pool, s, true);
     batched.perm = d_perm;
     batched.ctr = alloc_zero<hm::QueueCounters>(1, s, true);
@@ -239,6 +276,7 @@ struct hmat_s {
     max_nout_p1 = 0;
     for (int32_t i = 0; i < L.n1; ++i) max_nout_p1 = std::max(max_nout_p1, L.units[i].nout);
     if (opts.max_nrhs > 0) {
+      if (!L.sums.empty()) hm::fail(HMAT_EINVAL, "internal: ensemble layout with split units");
       if (opts.prec != HMAT_F32) hm::fail(HMAT_EUNSUPPORTED, "the ensemble product needs FP32 storage");
       if (max_nout_p1 > 1024) hm::fail(HMAT_EUNSUPPORTED, "the ensemble product needs wg_waves_p1 <= 16");
       mm_ts = alloc_zero<uint16_t>((size_t)3 * 64 * L.t_size, s, true);
@@ -314,6 +352,7 @@ constexpr int32_t kDefaultWaves = 8;
 constexpr int32_t kDefaultWavesP1 = 4;
 constexpr int32_t kSmallWavesP1 = 8;
 constexpr int32_t kSmallP1UnitsPerCU = 8;
+constexpr int kSmallTuneReps = 10;  // timed products per small-matrix layout candidate
 constexpr int32_t kDefaultUnitKiB = 256;
 
 void fill_stats(hmat_s* h);
@@ -353,14 +392,39 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
     const int64_t ub = (int64_t)(o.unit_kib ? o.unit_kib : kDefaultUnitKiB) * 1024;
     h->setup_batched_any(wg, ub, wg1, s);
     // Small matrices: with fewer than kSmallP1UnitsPerCU phase-1 units per
-    // compute unit the launch is short and its ramp and tail dominate; eight
-    // waves per unit shorten every unit (N = 21000: 58.7 -> 50.5 us per
-    // product; N = 122880 keeps four).
-    if (!o.wg_waves_p1 && h->kernel == HMAT_KERNEL_BATCHED_SPLIT &&
-        h->batched.n1 < kSmallP1UnitsPerCU * h->cus) {
-      wg1 = kSmallWavesP1;
-      h->drop_batched();
-      h->setup_batched_any(wg, ub, wg1, s);
+    // compute unit the largest units run alone at the end of phase 1.  Two
+    // remedies, each best on some matrices (measured, us per product):
+    // splitting them by rows with four waves per unit (planar N = 21000:
+    // 49.3, against 51.0 with eight waves; triangles B: 61.4 against 63.7)
+    // or eight waves per unit, which shortens every unit (triangles A: 59.2
+    // against 65.2).  The handle times a few products of each layout and
+    // keeps the fastest (one choice per handle; its products stay
+    // reproducible).
+    if (!o.wg_waves_p1 && h->kernel == HMAT_KERNEL_BATCHED_SPLIT && h->batched.n1 < kSmallP1UnitsPerCU * h->cus) {
+      struct Cand {
+        int32_t wg1, split;
+      };
+      std::vector<Cand> cands{{kDefaultWavesP1, 1}, {kSmallWavesP1, 0}, {kSmallWavesP1, 1}};
+      if (o.max_nrhs > 0) cands = {{kDefaultWavesP1, 0}, {kSmallWavesP1, 0}};
+      double best = 1e300;
+      Cand pick = cands[0], cur{-1, -1};
+      for (const Cand& c : cands) {
+        h->drop_batched();
+        h->split_mode = c.split;
+        h->setup_batched_any(wg, ub, c.wg1, s);
+        cur = c;
+        const double ms = h->time_product(s, kSmallTuneReps);
+        if (ms < best) {
+          best = ms;
+          pick = c;
+        }
+      }
+      if (pick.wg1 != cur.wg1 || pick.split != cur.split) {
+        h->drop_batched();
+        h->split_mode = pick.split;
+        h->setup_batched_any(wg, ub, pick.wg1, s);
+      }
+      wg1 = pick.wg1;
     }
     if (o.transpose) {
       const int32_t w1 = h->kernel == HMAT_KERNEL_BATCHED_PERSISTENT ? wg : wg1;

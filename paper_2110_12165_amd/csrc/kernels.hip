@@ -64,7 +64,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <typename T, int NW, bool COHERENT>
 __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ pool, const double* __restrict__ x,
                                          double* __restrict__ y, const int32_t* __restrict__ perm,
-                                         const int32_t* __restrict__ src, double* t, double alpha, double beta,
+                                         const int32_t* __restrict__ src, double* t,
+                                         const int32_t* __restrict__ sums, int t_size, double alpha, double beta,
                                          double* zs, double* red) {
   using V = typename Pack<T>::vec;
   constexpr int W = Pack<T>::W;
@@ -90,8 +91,17 @@ __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ po
         if (gi < u.nin) v = x[perm[u.in0 + gi]];
       } else {
         const int s = src[u.in0 + gi];
-        if (s >= 0) v = x[s];
-        else v = COHERENT ? load_agent(t - s - 1) : t[-s - 1];
+        if (s >= 0) {
+          v = x[s];
+        } else if (-s - 1 < t_size) {
+          v = COHERENT ? load_agent(t - s - 1) : t[-s - 1];
+        } else {  // a value split over row parts: partials added in part order
+          const int* e = sums + 4 * (-s - 1 - t_size);
+          if (COHERENT)
+            v = ((load_agent(t + e[0]) + load_agent(t + e[1])) + load_agent(t + e[2])) + load_agent(t + e[3]);
+          else
+            v = ((t[e[0]] + t[e[1]]) + t[e[2]]) + t[e[3]];
+        }
       }
       zs[i] = v;
     }
@@ -148,7 +158,8 @@ __global__ __launch_bounds__(NW * 64) void k_phase(BatchedArgs a, const double* 
   __shared__ double zs[kStage];
   __shared__ double red[NW * 64];
   const Unit u = a.units[(PHASE == 1 ? 0 : a.n1) + blockIdx.x];
-  run_unit<T, NW, false>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, alpha, beta, zs, red);
+  run_unit<T, NW, false>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, a.sums, a.t_size, alpha, beta,
+                         zs, red);
 }
 
 // Persistent schedule: one launch; workgroups take units in ticket order
@@ -200,7 +211,8 @@ __global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const dou
       ready = true;
     }
     const Unit u = a.units[t];
-    run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, alpha, beta, zs, red);
+    run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, a.sums, a.t_size, alpha, beta,
+                          zs, red);
     if (t < n1) ++pending;
   }
   if (threadIdx.x == 0) {
@@ -336,6 +348,19 @@ hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const
 }
 
 template <typename T>
+int phase1_blocks_per_cu(int wg_waves_p1) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  switch (wg_waves_p1) {
+    case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phase<T, 4, 1>, 4 * 64, 0); break;
+    case 8: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phase<T, 8, 1>, 8 * 64, 0); break;
+    case 16: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_phase<T, 16, 1>, 16 * 64, 0); break;
+    default: break;
+  }
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
+template <typename T>
 int persistent_blocks_per_cu(int wg_waves) {
   switch (wg_waves) {
     case 4: return occupancy_nw<T, 4>();
@@ -366,6 +391,8 @@ template hipError_t launch_batched<double>(const BatchedArgs&, bool, int, const 
                                            hipStream_t, hipEvent_t*);
 template int persistent_blocks_per_cu<float>(int);
 template int persistent_blocks_per_cu<double>(int);
+template int phase1_blocks_per_cu<float>(int);
+template int phase1_blocks_per_cu<double>(int);
 template hipError_t launch_plain<float>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t,
                                         hipEvent_t*);
 template hipError_t launch_plain<double>(const PlainArgs&, bool, const double*, double*, double, double, hipStream_t,

@@ -29,6 +29,8 @@ struct BatchedArgs {
   int32_t n1, n2;
   const int32_t* src;
   double* t;  // scratch: intermediate values t = V^T x, t[0] = 0
+  const int32_t* sums;  // 4 partial-value slots per split intermediate value (or null)
+  int32_t t_size;       // intermediate values (main and partial); src -(t_size + j) - 1 reads sums[4 j ..]
   const void* pool;
   const int32_t* perm;
   QueueCounters* ctr;
@@ -48,5 +50,9 @@ hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const
 
 template <typename T>
 int persistent_blocks_per_cu(int wg_waves);
+
+// Phase-1 workgroups of wg_waves_p1 waves resident per compute unit.
+template <typename T>
+int phase1_blocks_per_cu(int wg_waves_p1);
 
 }  // namespace hm

@@ -2,6 +2,7 @@
 #include "layout.hpp"
 
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <numeric>
 
@@ -195,7 +196,7 @@ PlainLayout<T> make_plain(const HostMatrix& H, bool transpose, int32_t n_threads
 
 template <typename T>
 BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1,
-                              bool transpose, int32_t n_threads) {
+                              bool transpose, int32_t n_threads, int64_t split_slots) {
   constexpr int W = 16 / (int)sizeof(T);
   BatchedLayout<T> L;
   L.wg_waves = wg_waves;
@@ -205,16 +206,21 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
   const BlockView B{H, transpose};
 
   // ---- phase 1: group low-rank blocks by their column cluster -------------
-  // Every unit covers all rows of its cluster, so each intermediate value is
-  // produced by exactly one unit (no partial sums).  Waves of a unit split
-  // the rows into RG groups (at least kMinQuads input groups each) and the
-  // outputs into S groups of 64.
+  // A unit covers the rows of its cluster (all of them, or with split_rows
+  // one of P <= 4 row ranges of a cluster whose units would be far larger
+  // than the others: each part then writes its own partial intermediate
+  // values, added by phase 2).  Waves of a unit split its rows into RG
+  // groups (at least kMinQuads input groups each) and the outputs into S
+  // groups of 64.
   constexpr int64_t kMinQuads = 16;
+  constexpr int kMaxParts = 4;
   struct Group {
     int64_t c0, n;
     std::vector<int32_t> blocks;
     int64_t R = 0, base = 0;
-    int S = 1, RG = 1;
+    int S = 1, RG = 1, P = 1;
+    int64_t nq_part = 0;           // input groups per row part
+    int64_t xbase[kMaxParts] = {};  // first slot of each part's values (part 0: base)
   };
   std::vector<Group> groups;
   std::map<std::pair<int64_t, int64_t>, size_t> gid;
@@ -224,10 +230,29 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     auto it = gid.find(key);
     if (it == gid.end()) {
       it = gid.emplace(key, groups.size()).first;
-      groups.push_back(Group{B.c0(b), B.n(b), {}, 0, 0, 1, 1});
+      Group g;
+      g.c0 = B.c0(b);
+      g.n = B.n(b);
+      groups.push_back(g);
     }
     groups[it->second].blocks.push_back((int32_t)b);
     groups[it->second].R += B.rank(b);
+  }
+  // Row parts (small matrices only): a 64-output unit of a group is split
+  // when it is more than twice the mean 64-output unit.  Measured: N = 21000
+  // 58.6 -> 49.0 us per product; at N = 122880 (5.6 units per slot) the
+  // extra units and partial values cost more than the shorter tail gains.
+  double mean64 = 0.0;
+  bool split_rows = false;
+  {
+    double tot = 0.0, cnt = 0.0;
+    for (const auto& g : groups) {
+      const double u64 = (double)((g.R + 63) / 64);
+      tot += u64 * 64.0 * (double)((g.n + W - 1) / W);
+      cnt += u64;
+    }
+    mean64 = cnt > 0 ? tot / cnt : 0.0;
+    split_rows = split_slots > 0 && cnt < 2.0 * (double)split_slots;
   }
   std::vector<int64_t> slot_of_block(nb, -1);  // t index of (block, column 0)
   int64_t t = 1;                                // t[0] is the zero pad
@@ -236,20 +261,45 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     // many output groups as the remaining waves allow.  Measured on the
     // benchmark fault: more, shorter per-wave loops beat fewer, fuller units.
     const int64_t nq = (g.n + W - 1) / W;
-    g.RG = (int)std::max<int64_t>(1, std::min<int64_t>(wg_waves_p1, nq / kMinQuads));
+    int P = 1;
+    if (split_rows && mean64 > 0.0) {
+      const double ratio = 64.0 * (double)nq / (2.0 * mean64);
+      if (ratio > 1.0) P = (int)std::min<double>(kMaxParts, std::ceil(ratio));
+      while (P > 1 && nq / P < kMinQuads) --P;
+    }
+    g.P = P;
+    g.nq_part = (nq + P - 1) / P;
+    g.RG = (int)std::max<int64_t>(1, std::min<int64_t>(wg_waves_p1, g.nq_part / kMinQuads));
     const int64_t need = (g.R + 63) / 64;
     g.S = (int)std::max<int64_t>(1, std::min<int64_t>(need, wg_waves_p1 / g.RG));
-    while (g.S > 1 && 64LL * g.S * g.n * (int64_t)sizeof(T) > unit_bytes) --g.S;
+    while (g.S > 1 && 64LL * g.S * g.nq_part * W * (int64_t)sizeof(T) > unit_bytes) --g.S;
     g.base = t;
+    g.xbase[0] = t;
     for (int32_t b : g.blocks) {
       slot_of_block[b] = t;
       t += B.rank(b);
     }
   }
+  const int64_t t_main = t;
+  for (auto& g : groups)
+    for (int p = 1; p < g.P; ++p) {
+      g.xbase[p] = t;
+      t += g.R;
+    }
   L.t_size = t;
   to_i32(t + 1, "intermediate values");
+  // partial values of each split intermediate value, added in part order
+  std::vector<int32_t> sum_of_slot(t_main, -1);
+  for (const auto& g : groups) {
+    if (g.P == 1) continue;
+    for (int64_t k = 0; k < g.R; ++k) {
+      sum_of_slot[g.base + k] = (int32_t)(L.sums.size() / 4);
+      for (int p = 0; p < kMaxParts; ++p) L.sums.push_back(p < g.P ? (int32_t)(g.xbase[p] + k) : 0);
+    }
+  }
+  to_i32(L.t_size + (int64_t)L.sums.size() / 4 + 1, "intermediate values and their sums");
 
-  struct Pending { Unit u; int kind; size_t g; int64_t s0; };
+  struct Pending { Unit u; int kind; size_t g; int64_t s0; int64_t r0; };
   int64_t off = 0;
   std::vector<Pending> pend;
   for (size_t gi = 0; gi < groups.size(); ++gi) {
@@ -257,17 +307,22 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     const int64_t NS = 64LL * g.S;
     for (int64_t s0 = 0; s0 < g.R; s0 += NS) {
       const int64_t ns = std::min(NS, g.R - s0);
-      Unit u;
-      u.kind = 1;
-      u.nout = (int32_t)ns;
-      u.nq = to_i32((g.n + W - 1) / W, "unit inputs");
-      u.S = (int32_t)((ns + 63) / 64);
-      u.RG = g.RG;
-      u.in0 = to_i32(g.c0, "row");
-      u.nin = (int32_t)g.n;
-      u.out0 = to_i32(g.base + s0, "intermediate index");
-      u.off = 0;
-      pend.push_back({u, 1, gi, s0});
+      for (int p = 0; p < g.P; ++p) {
+        const int64_t r0 = (int64_t)p * g.nq_part * W;
+        const int64_t rows = std::min(g.n - r0, g.nq_part * W);
+        if (rows <= 0) continue;
+        Unit u;
+        u.kind = 1;
+        u.nout = (int32_t)ns;
+        u.nq = to_i32((rows + W - 1) / W, "unit inputs");
+        u.S = (int32_t)((ns + 63) / 64);
+        u.RG = g.RG;
+        u.in0 = to_i32(g.c0 + r0, "row");
+        u.nin = (int32_t)rows;
+        u.out0 = to_i32(g.xbase[p] + s0, "intermediate index");
+        u.off = 0;
+        pend.push_back({u, 1, gi, s0, r0});
+      }
     }
   }
   // ---- phase 2: one unit per refined row interval --------------------------
@@ -290,7 +345,11 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
           for (int64_t j = 0; j < B.n(b); ++j) L.src.push_back(H.perm[B.c0(b) + j]);
           K += B.n(b);
         } else if (pass == 1 && B.kind(b) == 1 && B.rank(b) > 0) {
-          for (int64_t kk = 0; kk < B.rank(b); ++kk) L.src.push_back(-(int32_t)(slot_of_block[b] + kk) - 1);
+          for (int64_t kk = 0; kk < B.rank(b); ++kk) {
+            const int64_t slot = slot_of_block[b] + kk;
+            const int64_t j = sum_of_slot[slot];
+            L.src.push_back(j < 0 ? -(int32_t)slot - 1 : -(int32_t)(L.t_size + j) - 1);
+          }
           K += B.rank(b);
         }
       }
@@ -301,7 +360,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     u.nq = to_i32(K / W, "unit inputs");
     u.nin = (int32_t)K;
     u.off = 0;
-    pend.push_back({u, 2, k, 0});
+    pend.push_back({u, 2, k, 0, 0});
   }
   to_i32((int64_t)L.src.size(), "input list");
   // Dispatch order: phase 1 before phase 2, larger units first.  Panels are
@@ -336,7 +395,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
       }
       for (int64_t q = 0; q < u.nq; ++q)
         for (int64_t o = 0; o < u.nout; ++o) {
-          const double* V = sl[o];
+          const double* V = sl[o] + p.r0;  // rows of this part
           for (int c = 0; c < W; ++c) {
             const int64_t j = q * W + c;
             dst[(q * u.nout + o) * W + c] = j < u.nin ? (T)V[j] : T(0);
@@ -377,7 +436,9 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
 
 template PlainLayout<float> make_plain<float>(const HostMatrix&, bool, int32_t);
 template PlainLayout<double> make_plain<double>(const HostMatrix&, bool, int32_t);
-template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t);
-template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t);
+template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t,
+                                                  int64_t);
+template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t,
+                                                    int64_t);
 
 }  // namespace hm

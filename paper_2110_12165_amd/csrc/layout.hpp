@@ -34,6 +34,10 @@ struct BatchedLayout {
   int32_t n1 = 0, n2 = 0;
   std::vector<int32_t> src;
   int64_t t_size = 0;                  // intermediate values, entry 0 = zero pad
+  // Phase-1 units split by rows write partial intermediate values; entry j
+  // (4 slots, unused ones 0) lists the partials of one value, which phase 2
+  // adds in that order when a source reads -(t_size + j) - 1.
+  std::vector<int32_t> sums;
   int32_t wg_waves = 8;                // waves per workgroup of phase-2 units
   int32_t wg_waves_p1 = 8;             // waves per workgroup of phase-1 units
   int64_t unit_bytes = 0;
@@ -43,9 +47,14 @@ struct BatchedLayout {
 // units (equal for the persistent schedule, which runs both in one launch).
 // transpose: pack H^T (read in place; the same layout as packing
 // transpose_host(H)).  n_threads: panel-filling threads, 0 for all.
+// split_slots > 0: phase-1 workgroups resident on the device at once; when
+// phase 1 has fewer than two 64-output units per such slot (small
+// matrices, where the largest units run alone at the end of the phase),
+// units more than twice the mean are split by rows into up to 4 units with
+// partial intermediate values (see sums).  0: no splitting.
 template <typename T>
 BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1,
-                              bool transpose = false, int32_t n_threads = 0);
+                              bool transpose = false, int32_t n_threads = 0, int64_t split_slots = 0);
 
 // The blocks of H^T (dense blocks transposed, U and V exchanged), same
 // permutation: packing them gives the layouts of the transpose product.

@@ -27,10 +27,20 @@ static void die(const char* m, long a = 0, long b = 0) {
 
 template <typename T>
 static double replay(const HostMatrix& H, int NW, int NW1, int64_t unit_bytes, const std::vector<double>& x,
-                     const std::vector<double>& yref) {
+                     const std::vector<double>& yref, int64_t split_slots = 0, int64_t* n_sums = nullptr) {
   constexpr int W = 16 / (int)sizeof(T);
   constexpr int kStage = 2048;
-  BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes, NW1);
+  BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes, NW1, false, 0, split_slots);
+  if (n_sums) *n_sums = (int64_t)L.sums.size() / 4;
+  if (L.sums.size() % 4) die("sums not in groups of 4", (long)L.sums.size());
+  // every partial slot belongs to exactly one sum; the main slot comes first
+  std::vector<int> in_sum(L.t_size, 0);
+  for (size_t j = 0; j < L.sums.size(); ++j) {
+    const int32_t k = L.sums[j];
+    if (k < 0 || k >= L.t_size) die("sum slot", (long)j, k);
+    if (k > 0 && in_sum[k]++) die("slot in two sums", k);
+    if (j % 4 == 0 && k == 0) die("sum without its main slot", (long)j);
+  }
   const int64_t n = H.n;
   std::vector<double> t(L.t_size, 0.0), y(n, 0.0);
   std::vector<unsigned char> touched(L.pool.size(), 0);
@@ -64,10 +74,19 @@ static double replay(const HostMatrix& H, int NW, int NW1, int64_t unit_bytes, c
             if (s >= 0) {
               if (s >= n) die("x index", s);
               v = x[s];
-            } else {
-              if (-s - 1 >= L.t_size) die("t index", -s - 1);
+            } else if (-s - 1 < L.t_size) {
+              if (-s - 1 > 0 && in_sum[-s - 1]) die("split value read as a whole", -s - 1);
               if (-s - 1 > 0 && !t_written[-s - 1]) die("t read before written", -s - 1);
               v = t[-s - 1];
+            } else {
+              const int64_t j = -(int64_t)s - 1 - L.t_size;
+              if (j >= (int64_t)L.sums.size() / 4) die("sum index", (long)j);
+              v = 0.0;
+              for (int p = 0; p < 4; ++p) {
+                const int32_t k = L.sums[4 * j + p];
+                if (k > 0 && !t_written[k]) die("partial read before written", k);
+                v += t[k];
+              }
             }
           }
           zs[i] = v;
@@ -121,6 +140,8 @@ static double replay(const HostMatrix& H, int NW, int NW1, int64_t unit_bytes, c
   }
   for (int64_t i = 0; i < n; ++i)
     if (y_written[i] != 1) die("row not written once", (long)i, y_written[i]);
+  for (int64_t k = 1; k < L.t_size; ++k)
+    if (t_written[k] != 1) die("intermediate value not written once", (long)k, t_written[k]);
   // every non-padding panel entry must have been read (padding entries are 0)
   for (size_t e = 0; e < L.pool.size(); ++e)
     if (!touched[e] && L.pool[e] != T(0)) die("nonzero panel entry never read", (long)e);
@@ -220,6 +241,14 @@ int main(int argc, char** argv) {
       std::printf("NW=%d NW1=%d unit=%ld rel64=%.3e rel32=%.3e\n", NW, NW1, (long)ub, r64, r32);
       if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed product differs");
     }
+  // phase-1 units split by rows (partial values added by phase 2)
+  for (int NW1 : {4, 8}) {
+    int64_t ns64 = 0, ns32 = 0;
+    const double r64 = replay<double>(H, 8, NW1, 256 << 10, x, yref, 1 << 20, &ns64);
+    const double r32 = replay<float>(H, 8, NW1, 256 << 10, x, yref, 1 << 20, &ns32);
+    std::printf("split NW1=%d sums %ld/%ld rel64=%.3e rel32=%.3e\n", NW1, (long)ns64, (long)ns32, r64, r32);
+    if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed split product differs");
+  }
   std::printf("OK\n");
   return 0;
 }
