@@ -353,6 +353,7 @@ constexpr int32_t kDefaultWavesP1 = 4;
 constexpr int32_t kSmallWavesP1 = 8;
 constexpr int32_t kSmallP1UnitsPerCU = 8;
 constexpr int kSmallTuneReps = 10;  // timed products per small-matrix layout candidate
+constexpr int32_t kSmallWavesP2 = 4;
 constexpr int32_t kDefaultUnitKiB = 256;
 
 void fill_stats(hmat_s* h);
@@ -387,7 +388,7 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
     if (h->f32()) h->setup_plain<float>(o.transpose != 0, s);
     else h->setup_plain<double>(o.transpose != 0, s);
   } else {
-    const int32_t wg = o.wg_waves ? o.wg_waves : kDefaultWaves;
+    int32_t wg = o.wg_waves ? o.wg_waves : kDefaultWaves;
     int32_t wg1 = o.wg_waves_p1 ? o.wg_waves_p1 : kDefaultWavesP1;
     const int64_t ub = (int64_t)(o.unit_kib ? o.unit_kib : kDefaultUnitKiB) * 1024;
     h->setup_batched_any(wg, ub, wg1, s);
@@ -397,21 +398,24 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
     // splitting them by rows with four waves per unit (planar N = 21000:
     // 49.3, against 51.0 with eight waves; triangles B: 61.4 against 63.7)
     // or eight waves per unit, which shortens every unit (triangles A: 59.2
-    // against 65.2).  The handle times a few products of each layout and
-    // keeps the fastest (one choice per handle; its products stay
+    // against 65.2); phase 2 with four waves per unit also wins on some
+    // (planar N = 21000: 47.5 against 48.9) and loses on others (N = 7680:
+    // 21.3 against 18.1).  The handle times a few products of each layout
+    // and keeps the fastest (one choice per handle; its products stay
     // reproducible).
     if (!o.wg_waves_p1 && h->kernel == HMAT_KERNEL_BATCHED_SPLIT && h->batched.n1 < kSmallP1UnitsPerCU * h->cus) {
       struct Cand {
-        int32_t wg1, split;
+        int32_t wg, wg1, split;
       };
-      std::vector<Cand> cands{{kDefaultWavesP1, 1}, {kSmallWavesP1, 0}, {kSmallWavesP1, 1}};
-      if (o.max_nrhs > 0) cands = {{kDefaultWavesP1, 0}, {kSmallWavesP1, 0}};
+      std::vector<Cand> cands{{wg, kDefaultWavesP1, 1}, {wg, kSmallWavesP1, 0}, {wg, kSmallWavesP1, 1}};
+      if (!o.wg_waves) cands.push_back({kSmallWavesP2, kDefaultWavesP1, 1});
+      if (o.max_nrhs > 0) cands = {{wg, kDefaultWavesP1, 0}, {wg, kSmallWavesP1, 0}};
       double best = 1e300;
-      Cand pick = cands[0], cur{-1, -1};
+      Cand pick = cands[0], cur{-1, -1, -1};
       for (const Cand& c : cands) {
         h->drop_batched();
         h->split_mode = c.split;
-        h->setup_batched_any(wg, ub, c.wg1, s);
+        h->setup_batched_any(c.wg, ub, c.wg1, s);
         cur = c;
         const double ms = h->time_product(s, kSmallTuneReps);
         if (ms < best) {
@@ -419,11 +423,12 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
           pick = c;
         }
       }
-      if (pick.wg1 != cur.wg1 || pick.split != cur.split) {
+      if (pick.wg != cur.wg || pick.wg1 != cur.wg1 || pick.split != cur.split) {
         h->drop_batched();
         h->split_mode = pick.split;
-        h->setup_batched_any(wg, ub, pick.wg1, s);
+        h->setup_batched_any(pick.wg, ub, pick.wg1, s);
       }
+      wg = pick.wg;
       wg1 = pick.wg1;
     }
     if (o.transpose) {
