@@ -444,6 +444,29 @@ def nonplanar_rk(torch, hm, f, w, n_steps):
     return out
 
 
+def autotune(torch, hm, f, w, x, steps, warmup):
+    """hmat_autotune on the benchmark matrix: it times the plain product and
+    every batched schedule (waves per workgroup of both phases, split or
+    persistent launch) on the handle's own blocks and keeps the fastest;
+    reports its pick and the product rate with it."""
+    from synth.faults import MU, NU
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
+                         lattice=w["lattice"], prec="f32", kernel="auto", transpose=0, build_device=1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = H.autotune(reps=10)
+    tune_s = time.perf_counter() - t0
+    y = torch.empty_like(x)
+    ms, _, _ = time_products(torch, H, x, y, steps, warmup)
+    H.close()
+    torch.cuda.empty_cache()
+    out = {"picked": {"kernel": info["kernel"], "wg_waves": info["wg_waves"], "wg_waves_p1": info["wg_waves_p1"]},
+           "autotune_s": tune_s, "matvec_per_s": 1e3 / ms, "ms": ms}
+    log(f"[bench] autotune: picked {info['kernel']} {info['wg_waves']}/{info['wg_waves_p1']} waves in {tune_s:.1f} s; "
+        f"{1e3 / ms:.1f} matvec/s with it")
+    return out
+
+
 def construction(torch, hm, f, opts, x):
     """Build time of the headline matrix (FP32 batched, with the transposed
     layout) from the element geometry: host ACA on all host threads versus
@@ -612,6 +635,7 @@ def main():
     ap.add_argument("--no-nonplanar", action="store_true", help="skip the triangle-mesh section")
     ap.add_argument("--no-construction", action="store_true", help="skip the host/device build timing")
     ap.add_argument("--no-sweeps", action="store_true", help="skip the size and lattice sweeps")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the autotuner run")
     ap.add_argument("--ens-rk-steps", type=int, default=100,
                     help="steps per member of the ensemble integration (0: skip)")
     ap.add_argument("--adjoint-steps", type=int, default=500,
@@ -746,6 +770,8 @@ def main():
         line["rel_diff_f32_vs_f64_gpu"] = float(np.linalg.norm(outputs["batched_f32"] - ref) / np.linalg.norm(ref))
     if not args.no_construction:
         line["construction"] = construction(torch, hm, f, bench_options(WORKLOAD, "batched_f32"), x)
+    if not args.no_autotune:
+        line["autotune"] = autotune(torch, hm, f, w, x, args.steps, args.warmup)
     if not args.no_sweeps:
         line["sweeps"] = sweeps(torch, hm)
     if args.rk_steps > 0:
