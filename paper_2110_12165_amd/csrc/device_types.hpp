@@ -45,9 +45,23 @@ struct Unit {
   int64_t off;
 };
 
-// Counters of the persistent schedule; reset by the last workgroup to exit.
+// Counters of the persistent schedule, each in its own 128-byte line and
+// sharded over kShards addresses (workgroup b uses shard b % kShards), so
+// that no single address takes an atomic from every workgroup: on this GPU
+// device-scope atomics on one address are served one at a time.  Reset by
+// the last workgroup to exit.
+constexpr int kShards = 8;
+struct alignas(128) PaddedCounter {
+  uint32_t v;
+  uint32_t pad[31];
+};
 struct QueueCounters {
-  uint32_t next, p1done, exited, pad;
+  PaddedCounter tick1[kShards];   // phase-1 tickets; shard s hands out units s, s + kShards, ...
+  PaddedCounter tick2[kShards];   // phase-2 tickets (unit indices relative to n1)
+  PaddedCounter done1[kShards];   // phase-1 units finished, counted by the finishing workgroup's shard
+  PaddedCounter exited[kShards];  // workgroups of the shard that have exited
+  PaddedCounter exited_all;       // shards whose workgroups have all exited
+  PaddedCounter error;            // set if a wait gave up (results of that launch invalid)
 };
 
 }  // namespace hm

@@ -162,65 +162,111 @@ __global__ __launch_bounds__(NW * 64) void k_phase(BatchedArgs a, const double* 
                          zs, red);
 }
 
-// Persistent schedule: one launch; workgroups take units in ticket order
-// (all phase-1 units come first).  Thread 0 alone touches the ticket counter,
-// in a region at the top of the loop followed by a barrier.  Cross-workgroup
-// visibility of the intermediate values costs an L2 write-back / invalidate
-// on this GPU, so it is paid at most once per workgroup and direction:
-//   - a workgroup counts the phase-1 units it finished and publishes the
-//     count (after every thread's release fence) only when it draws its
-//     first phase-2 ticket or runs out of work;
-//   - before its first phase-2 unit, wave 0 waits (acquire) until the
-//     published count reaches n1; later units skip the wait.
-// A workgroup publishes before it waits, and every phase-1 unit is held by a
-// running workgroup once any phase-2 ticket exists, so the wait ends.
+// Persistent schedule: one launch of resident workgroups that take units by
+// ticket until none is left, phase 1 before phase 2.
+//   * Tickets are sharded: shard s hands out units s, s + kShards, ...; a
+//     workgroup draws from its own shard (blockIdx % kShards) and, once that
+//     is exhausted, from the others in turn, one ticket after each unit
+//     (drawing the next one early made workgroups hold two of the largest
+//     units at once and ran slower).
+//   * A workgroup that finds no phase-1 unit left in any shard adds the
+//     number of phase-1 units it finished to its shard's done1 (after a
+//     release fence) and waits until the done1 counts sum to n1; it then
+//     acquires and goes on with phase 2.  Every phase-1 unit was claimed by a
+//     running workgroup before any workgroup waits, so the wait ends; it is
+//     bounded all the same (kSpinLimit polls, then the error counter is set
+//     and the workgroup skips phase 2).
+//   * The last workgroup of each shard to exit counts the shard in
+//     exited_all; the last shard resets every counter for the next launch.
+constexpr unsigned kSpinLimit = 1u << 22;
+
+__device__ __forceinline__ unsigned atomic_add_agent(uint32_t* p, unsigned v) {
+  return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned load_agent_u(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ int shard_units(int n, int s) { return n > s ? (n - s + kShards - 1) / kShards : 0; }
+
+// Thread 0 only: the unit of ticket tk drawn on shard sh, or a ticket of the
+// next shards once sh is exhausted; -1 when every shard is.
+__device__ int resolve_ticket(PaddedCounter* tick, int n, int& sh, int& tried, unsigned tk) {
+  for (;;) {
+    if (tk < (unsigned)shard_units(n, sh)) return sh + kShards * (int)tk;
+    if (++tried >= kShards) return -1;
+    sh = (sh + 1) % kShards;
+    tk = load_agent_u(&tick[sh].v) >= (unsigned)shard_units(n, sh) ? 0xffffffffu : atomic_add_agent(&tick[sh].v, 1u);
+  }
+}
+
 template <typename T, int NW>
 __global__ __launch_bounds__(NW * 64) void k_persistent(BatchedArgs a, const double* __restrict__ x,
                                                         double* __restrict__ y, double alpha, double beta) {
   __shared__ double zs[kStage];
   __shared__ double red[NW * 64];
-  __shared__ unsigned ticket;
-  const unsigned n1 = (unsigned)a.n1, total = (unsigned)(a.n1 + a.n2);
-  QueueCounters* ctr = a.ctr;
-  const int wave = threadIdx.x >> 6;
-  unsigned pending = 0;  // phase-1 units finished, not yet published (uniform)
-  bool ready = false;    // this workgroup has seen all phase-1 units done (uniform)
-  for (;;) {
-    if (threadIdx.x == 0) ticket = __hip_atomic_fetch_add(&ctr->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __syncthreads();
-    const unsigned t = __builtin_amdgcn_readfirstlane(ticket);
-    __syncthreads();
-    if (t >= n1 && pending) {
-      __threadfence();
+  __shared__ int s_unit;
+  QueueCounters* q = a.ctr;
+  const int own = (int)(blockIdx.x % kShards);
+  const T* pool = static_cast<const T*>(a.pool);
+  bool ok = true;
+  for (int phase = 1; phase <= 2 && ok; ++phase) {
+    PaddedCounter* tick = phase == 1 ? q->tick1 : q->tick2;
+    const int n = phase == 1 ? a.n1 : a.n2;
+    const int base = phase == 1 ? 0 : a.n1;
+    int sh = own, tried = 0, done = 0;
+    for (;;) {
+      if (threadIdx.x == 0) s_unit = resolve_ticket(tick, n, sh, tried, atomic_add_agent(&tick[sh].v, 1u));
       __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(&ctr->p1done, pending, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      pending = 0;
+      const int cur = __builtin_amdgcn_readfirstlane(s_unit);
+      __syncthreads();
+      if (cur < 0) break;
+      run_unit<T, NW, true>(a.units[base + cur], pool, x, y, a.perm, a.src, a.t, a.sums, a.t_size, alpha, beta, zs,
+                            red);
+      ++done;
     }
-    if (t >= total) break;
-    if (t >= n1 && !ready) {
-      if (wave == 0) {
-        for (;;) {
-          const unsigned d = __builtin_amdgcn_readfirstlane(
-              __hip_atomic_load(&ctr->p1done, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
-          if (d >= n1) break;
+    if (phase == 1) {
+      // publish, then wait for every phase-1 unit
+      if (threadIdx.x == 0 && done > 0) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        atomic_add_agent(&q->done1[own].v, (unsigned)done);
+      }
+      if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        for (unsigned spins = 0;; ++spins) {
+          unsigned v = lane < kShards ? load_agent_u(&q->done1[lane].v) : 0u;
+#pragma unroll
+          for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+          if (__builtin_amdgcn_readfirstlane(v) >= (unsigned)a.n1) break;
+          if (spins >= kSpinLimit) {
+            if (lane == 0) atomic_add_agent(&q->error.v, 1u);
+            ok = false;
+            break;
+          }
           __builtin_amdgcn_s_sleep(2);
         }
+        if (threadIdx.x == 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
       }
+      if (threadIdx.x == 0) s_unit = ok ? 1 : 0;
       __syncthreads();
-      ready = true;
+      ok = __builtin_amdgcn_readfirstlane(s_unit) != 0;
+      __syncthreads();
     }
-    const Unit u = a.units[t];
-    run_unit<T, NW, true>(u, static_cast<const T*>(a.pool), x, y, a.perm, a.src, a.t, a.sums, a.t_size, alpha, beta,
-                          zs, red);
-    if (t < n1) ++pending;
   }
   if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(&ctr->exited, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    if (prev == gridDim.x - 1) {
-      __hip_atomic_store(&ctr->next, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctr->p1done, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctr->exited, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const int in_shard = (int)((gridDim.x - own + kShards - 1) / kShards);
+    const unsigned prev = __hip_atomic_fetch_add(&q->exited[own].v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int)prev == in_shard - 1) {
+      const unsigned shards = gridDim.x < (unsigned)kShards ? gridDim.x : (unsigned)kShards;
+      const unsigned p2 = __hip_atomic_fetch_add(&q->exited_all.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (p2 == shards - 1) {
+        for (int s = 0; s < kShards; ++s) {
+          __hip_atomic_store(&q->tick1[s].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&q->tick2[s].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&q->done1[s].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&q->exited[s].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __hip_atomic_store(&q->exited_all.v, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
   }
 }
