@@ -213,3 +213,37 @@ def test_autotune_and_profile(torch_dev, hm):
         assert pr["alg_bytes"][0] == st["alg_bytes"]
     assert rel(y.cpu().numpy(), ref) <= 1e-13
     Hg.close()
+
+
+@pytest.mark.parametrize("wg,wg1", [(8, 4), (4, 4), (8, 8)])
+def test_row_split_layouts(torch_dev, hm, wg, wg1):
+    """Small matrices split their oversized phase-1 units by rows, with the
+    partial intermediate values added by phase 2: parity with the oracle on
+    shared factors (FP64 to 1e-13, FP32 to 2e-5) and with the same handle
+    built whole (ensemble buffers keep units whole), forward and transposed,
+    bitwise reproducible."""
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case("dip30_150x70")
+    B = oracle_blocks(H)
+    x = loguniform_rates(f.n, 21)
+    xd = torch.tensor(x, device=dev)
+    ref, ref_t = H.matvec(x), H.matvec_T(x)
+    for prec, tol in (("f64", 1e-13), ("f32", 2e-5)):
+        Hs = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec=prec, kernel="split",
+                                    wg_waves=wg, wg_waves_p1=wg1)
+        ys = [Hs.matvec(xd).cpu().numpy() for _ in range(3)]
+        yt = Hs.matvec_T(xd).cpu().numpy()
+        n_split = Hs.info()["n_units_p1"]
+        Hs.close()
+        assert all(np.array_equal(y, ys[0]) for y in ys[1:])
+        assert rel(ys[0], ref) <= tol and rel(yt, ref_t) <= tol
+        if prec == "f32":   # the ensemble buffers need FP32 storage
+            Hw = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec=prec,
+                                        kernel="split", wg_waves=wg, wg_waves_p1=wg1, max_nrhs=8)
+            yw = Hw.matvec(xd).cpu().numpy()
+            n_whole = Hw.info()["n_units_p1"]
+            Hw.close()
+            say(f"[row split] waves {wg}/{wg1}: phase-1 units {n_split} split, {n_whole} whole")
+            assert rel(yw, ref) <= tol
+            if wg1 == 4:
+                assert n_split > n_whole   # the layout did split units
