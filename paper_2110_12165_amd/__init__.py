@@ -50,7 +50,8 @@ class HMatrix:
     # -- construction -------------------------------------------------------
     @staticmethod
     def _opts(aca_eps=1e-6, eta=2.0, leaf=32, lattice=1, max_rank=0, prec="f64", kernel="auto",
-              n_threads=0, wg_waves=0, unit_kib=0, wg_waves_p1=0, max_nrhs=0, transpose=1, build_device=0):
+              n_threads=0, wg_waves=0, unit_kib=0, wg_waves_p1=0, max_nrhs=0, transpose=1, build_device=0,
+              mm_groups=0):
         lib = _lib.load()
         o = _lib.HmatOpts()
         lib.hmat_default_opts(C.byref(o))
@@ -61,6 +62,7 @@ class HMatrix:
         o.max_nrhs = max_nrhs
         o.transpose = transpose
         o.build_device = build_device
+        o.mm_groups = mm_groups
         return o
 
     @classmethod
@@ -165,6 +167,8 @@ class HMatrix:
         d = {name: getattr(st, name) for name, _ in _lib.HmatStats._fields_}
         d["kernel"] = _lib.KERNEL_NAME.get(d["kernel"], d["kernel"])
         d["prec"] = "f32" if d["prec"] == 1 else "f64"
+        g = d.pop("mm_groups")
+        d["mm_groups"] = {"x3": ((g >> 0) & 15, (g >> 4) & 15), "x6": ((g >> 8) & 15, (g >> 12) & 15)} if g else None
         return d
 
     @property

@@ -31,7 +31,8 @@ class HmatOpts(C.Structure):
     _fields_ = [("aca_eps", C.c_double), ("eta", C.c_double), ("leaf", C.c_int32), ("lattice", C.c_int32),
                 ("max_rank", C.c_int32), ("prec", C.c_int32), ("kernel", C.c_int32), ("n_threads", C.c_int32),
                 ("wg_waves", C.c_int32), ("unit_kib", C.c_int32), ("wg_waves_p1", C.c_int32),
-                ("max_nrhs", C.c_int32), ("transpose", C.c_int32), ("build_device", C.c_int32)]
+                ("max_nrhs", C.c_int32), ("transpose", C.c_int32), ("build_device", C.c_int32),
+                ("mm_groups", C.c_int32)]
 
 
 class HmatStats(C.Structure):
@@ -39,7 +40,7 @@ class HmatStats(C.Structure):
         "n", "n_dense", "n_lr", "dense_entries", "lr_entries", "max_rank", "sum_rank", "n_leaves",
         "tree_depth", "device_bytes", "factor_bytes", "alg_bytes", "n_units_p1", "n_units_p2")] + [
         ("prec", C.c_int32), ("kernel", C.c_int32), ("wg_waves", C.c_int32), ("lattice", C.c_int32),
-        ("wg_waves_p1", C.c_int32), ("pad", C.c_int32)]
+        ("wg_waves_p1", C.c_int32), ("mm_groups", C.c_int32)]
 
 
 class HmatHostBlocks(C.Structure):

@@ -127,6 +127,8 @@ struct hmat_s {
   int32_t max_nout_p1 = 0;
   int32_t* mm_slices1 = nullptr;  // ensemble product: 64-output slices of the phase-1 units
   int32_t mm_ns1 = 0;
+  // ensemble product: wave groups per 64-output slice, [mode - BF16X3][phase - 1]
+  int32_t mm_groups[2][2] = {{1, 1}, {1, 1}};
   double* rs_x = nullptr;  // n doubles: slip rate minus plate rate (rs_rhs scratch)
   double* rs_ax = nullptr;  // n doubles: A (V - V_pl)
   double* rs_bx = nullptr;  // n doubles: B (V - V_pl)
@@ -254,6 +256,32 @@ struct hmat_s {
     return (double)ms / reps;
   }
 
+  hm::MMArgs mm_args(const double* X, int64_t ldx, double* Y, int64_t ldy, int32_t nrhs, int32_t mode) const {
+    hm::MMArgs a{};
+    a.units = batched.units;
+    a.n1 = batched.n1;
+    a.n2 = batched.n2;
+    a.slices1 = mm_slices1;
+    a.ns1 = mm_ns1;
+    a.cus = cus;
+    a.groups1 = mm_groups[mode - HMAT_MM_BF16X3][0];
+    a.groups2 = mm_groups[mode - HMAT_MM_BF16X3][1];
+    a.src = batched.src;
+    a.pool = batched.pool;
+    a.perm = d_perm;
+    a.invperm = d_invperm;
+    a.n = H.n;
+    a.t_size = t_size;
+    a.Xs = mm_xs;
+    a.Ts = mm_ts;
+    a.X = X;
+    a.ldx = ldx;
+    a.Y = Y;
+    a.ldy = ldy;
+    a.nrhs = nrhs;
+    return a;
+  }
+
   template <typename T>
   void setup_batched(int32_t wg, int64_t unit_bytes, int32_t wg1, hipStream_t s) {
     // Row-split phase-1 units write partial intermediate values that the
@@ -343,6 +371,7 @@ void check_opts(const hmat_opts& o, bool build) {
   if (o.max_nrhs < 0) hm::fail(HMAT_EINVAL, "max_nrhs must be >= 0");
   if (o.transpose != 0 && o.transpose != 1) hm::fail(HMAT_EINVAL, "transpose must be 0 or 1");
   if (o.build_device != 0 && o.build_device != 1) hm::fail(HMAT_EINVAL, "build_device must be 0 or 1");
+  if (o.mm_groups < 0 || o.mm_groups > 2) hm::fail(HMAT_EINVAL, "mm_groups must be 0, 1 or 2");
 }
 
 // Default schedule of the batched product (fastest measured on MI355X for
@@ -355,6 +384,58 @@ constexpr int32_t kSmallP1UnitsPerCU = 8;
 constexpr int kSmallTuneReps = 10;  // timed products per small-matrix layout candidate
 constexpr int32_t kSmallWavesP2 = 4;
 constexpr int32_t kDefaultUnitKiB = 256;
+constexpr int kMMTuneReps = 5;  // timed ensemble products per mode and wave-group count
+
+// Wave groups of the ensemble product.  Two groups per slice halve the
+// path of each workgroup and the workgroups resident per compute unit;
+// which wins depends on the unit sizes and counts in a way no simple rule
+// caught (measured, us per 64-member BF16x6 product, one / two groups in
+// phase 2: N = 7680 85 / 69, N = 21000 193 / 200, N = 30720 178 / 156;
+// phase 1, BF16x3: N = 21000 137 / 115, N = 122880 435 / 471).  Unless
+// hmat_opts.mm_groups forces a value, this times kMMTuneReps products of each
+// mode with one and with two groups, with events around each phase, and
+// keeps per phase and mode the faster (fixed for the handle, so its
+// products stay reproducible).  The timed products read zeros from a
+// temporary buffer.
+void tune_mm(hmat_s* h, hipStream_t s) {
+  if (h->opts.mm_groups) {
+    for (auto& m : h->mm_groups) m[0] = m[1] = h->opts.mm_groups;
+    return;
+  }
+  struct Buf {
+    void* p = nullptr;
+    ~Buf() { (void)hipFree(p); }
+  } bx, by;
+  struct Ev {
+    hipEvent_t e = nullptr;
+    Ev() { check_hip(hipEventCreate(&e), "hipEventCreate"); }
+    ~Ev() { (void)hipEventDestroy(e); }
+  } e[3];
+  const size_t bytes = (size_t)h->H.n * 64 * sizeof(double);
+  check_hip(hipMalloc(&bx.p, bytes), "hipMalloc");
+  check_hip(hipMalloc(&by.p, bytes), "hipMalloc");
+  check_hip(hipMemsetAsync(bx.p, 0, bytes, s), "hipMemsetAsync");
+  hipEvent_t ev[3] = {e[0].e, e[1].e, e[2].e};
+  for (int m = 0; m < 2; ++m) {
+    const int32_t mode = HMAT_MM_BF16X3 + m;
+    double ms[2][2] = {};  // [groups - 1][phase - 1]
+    for (int g = 0; g < 2; ++g) {
+      h->mm_groups[m][0] = h->mm_groups[m][1] = g + 1;
+      const hm::MMArgs a = h->mm_args(static_cast<const double*>(bx.p), 64, static_cast<double*>(by.p), 64, 64, mode);
+      for (int r = 0; r < 2 + kMMTuneReps; ++r) {
+        check_hip(hm::launch_mm(a, mode, 1.0, 0.0, s, ev), "ensemble launch");
+        check_hip(hipEventSynchronize(ev[2]), "hipEventSynchronize");
+        if (r < 2) continue;  // untimed
+        float t1 = 0.f, t2 = 0.f;
+        check_hip(hipEventElapsedTime(&t1, ev[0], ev[1]), "hipEventElapsedTime");
+        check_hip(hipEventElapsedTime(&t2, ev[1], ev[2]), "hipEventElapsedTime");
+        ms[g][0] += t1;
+        ms[g][1] += t2;
+      }
+    }
+    for (int p = 0; p < 2; ++p) h->mm_groups[m][p] = ms[1][p] < ms[0][p] ? 2 : 1;
+  }
+}
 
 void fill_stats(hmat_s* h);
 
@@ -431,6 +512,7 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
       wg = pick.wg;
       wg1 = pick.wg1;
     }
+    if (h->mm_xs) tune_mm(h.get(), s);
     if (o.transpose) {
       const int32_t w1 = h->kernel == HMAT_KERNEL_BATCHED_PERSISTENT ? wg : wg1;
       if (h->f32()) h->setup_batched_t<float>(wg, ub, w1, s);
@@ -481,6 +563,10 @@ void refresh_stats(hmat_s* h) {
   h->st.kernel = h->kernel;
   h->st.wg_waves = h->kernel == HMAT_KERNEL_PLAIN ? 0 : h->opts.wg_waves;
   h->st.wg_waves_p1 = h->kernel == HMAT_KERNEL_PLAIN ? 0 : h->opts.wg_waves_p1;
+  h->st.mm_groups = 0;
+  if (h->mm_xs)
+    for (int m = 0; m < 2; ++m)
+      for (int p = 0; p < 2; ++p) h->st.mm_groups |= h->mm_groups[m][p] << (4 * (2 * m + p));
 }
 
 void check_vectors(hmat_t h, const double* x, const double* y, int64_t nrhs, int64_t ld) {
@@ -616,26 +702,7 @@ namespace {
 // Ensemble product of up to 64 right-hand sides (X, Y element-major).
 void enqueue_mm(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, int32_t nrhs, double alpha,
                 double beta, int32_t mode, hipStream_t s) {
-  hm::MMArgs a{};
-  a.units = h->batched.units;
-  a.n1 = h->batched.n1;
-  a.n2 = h->batched.n2;
-  a.slices1 = h->mm_slices1;
-  a.ns1 = h->mm_ns1;
-  a.cus = h->cus;
-  a.src = h->batched.src;
-  a.pool = h->batched.pool;
-  a.perm = h->d_perm;
-  a.invperm = h->d_invperm;
-  a.n = h->H.n;
-  a.t_size = h->t_size;
-  a.Xs = h->mm_xs;
-  a.Ts = h->mm_ts;
-  a.X = X;
-  a.ldx = ldx;
-  a.Y = Y;
-  a.ldy = ldy;
-  a.nrhs = nrhs;
+  const hm::MMArgs a = h->mm_args(X, ldx, Y, ldy, nrhs, mode);
   check_hip(hm::launch_mm(a, mode, alpha, beta, s), "ensemble launch");
 }
 
@@ -728,6 +795,7 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
     h->drop_batched();
     h->kernel = best_k;
     if (best_k != HMAT_KERNEL_PLAIN) h->setup_batched_any(best_w, (int64_t)best_u * 1024, best_w1, s);
+    if (best_k != HMAT_KERNEL_PLAIN && h->mm_xs) tune_mm(h, s);
     refresh_stats(h);
   });
 }

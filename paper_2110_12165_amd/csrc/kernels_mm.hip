@@ -182,16 +182,21 @@ __device__ __forceinline__ void load_a(const float* pool, const Unit& u, int c0,
 
 // One workgroup per 64-output slice of a unit (phase-1 units with more than
 // 64 outputs are split into slices that stage the same inputs); wave w owns
-// the 16 outputs 16 w + [0, 16) of the slice and all 64 members.  Rounds are
-// software-pipelined: the members and panel quads of the next round are
-// loaded into registers while the MFMAs of the current round run, and
-// written to LDS after it.
-template <int NS, int PHASE, int KS>
-__global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, double beta) {
+// the 16 outputs 16 (w % 4) + [0, 16) of the slice and all 64 members.
+// G2 groups of four waves share a slice: group g takes rounds g, g + G2, ...
+// into its own LDS rows, and the groups' sums are added in group order at
+// the end.  G2 = 2 halves the path of every workgroup and the workgroups
+// resident per compute unit; the caller chooses per phase.  Rounds are software-pipelined:
+// the members and panel quads of a group's next round are loaded into
+// registers while the MFMAs of its current round run, and written to LDS
+// after it.
+template <int NS, int PHASE, int KS, int G2>
+__global__ __launch_bounds__(kWaves * 64 * G2) void k_mm(MMArgs a, double alpha, double beta) {
   __bf16* Ts = static_cast<__bf16*>(a.Ts);
   // bf16 bit patterns as 16-bit integers (whole vectors are bit-cast to bf16);
   // row = input of the round, 64 members, chunks swizzled by zchunk
-  __shared__ __attribute__((aligned(16))) unsigned short zs[NS][KS][kNR];
+  __shared__ __attribute__((aligned(16))) unsigned short zs[G2][NS][KS][kNR];
+  static_assert(sizeof(zs) >= (G2 > 1 ? kWaves * 64 * 16 * sizeof(float) : 0), "LDS too small for the group sums");
   int ui, ob = 0;
   if (PHASE == 1) {
     const int code = a.slices1[xcd_remap((int)blockIdx.x, (int)gridDim.x)];
@@ -203,27 +208,30 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
   const Unit u = a.units[ui];
   const float* pool = static_cast<const float*>(a.pool);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int grp = wave / kWaves, gw = wave % kWaves, gtid = tid % (kWaves * 64);
   const int lm = lane & 15, lk = lane >> 4;  // MFMA lane: row/col within 16, k group of 8
   const int ntiles = (min(u.nout, ob + 64) - ob + 15) >> 4;
   const int K = u.nq * 4;
   const int rounds = (K + KS - 1) / KS;
-  const int o = ob + wave * 16 + lm;
-  const bool work = wave < ntiles, orow = work && o < u.nout;
+  const int iters = (rounds + G2 - 1) / G2;  // rounds of one group (the last ones may be empty)
+  const int o = ob + gw * 16 + lm;
+  const bool work = gw < ntiles, orow = work && o < u.nout;
   f32x4 acc[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
   s16x8 sr[NS][items_of<KS>()];
   f32x4 ar[KS / 32][2], an[KS / 32][2];
-  stage_load<NS, PHASE, KS>(a, u, 0, K, tid, sr);
-  if (work) load_a(pool, u, 0, o, orow, lk, ar);
-  stage_store<NS, KS>(zs, tid, sr);
+  stage_load<NS, PHASE, KS>(a, u, grp * KS, K, gtid, sr);
+  if (work) load_a(pool, u, grp * KS, o, orow, lk, ar);
+  stage_store<NS, KS>(zs[grp], gtid, sr);
   __syncthreads();
 
-  for (int r = 0; r < rounds; ++r) {
-    const bool more = r + 1 < rounds;
+  for (int it = 0; it < iters; ++it) {
+    const bool more = it + 1 < iters;
+    const int next = ((it + 1) * G2 + grp) * KS;  // first input of this group's next round
     if (more) {
-      stage_load<NS, PHASE, KS>(a, u, (r + 1) * KS, K, tid, sr);
-      if (work) load_a(pool, u, (r + 1) * KS, o, orow, lk, an);
+      stage_load<NS, PHASE, KS>(a, u, next, K, gtid, sr);
+      if (work) load_a(pool, u, next, o, orow, lk, an);
     }
     if (work) {
 #pragma unroll
@@ -241,7 +249,8 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
         for (int nt = 0; nt < 4; ++nt) {
           bf16x8 bp[NS];
 #pragma unroll
-          for (int i = 0; i < NS; ++i) bp[i] = __builtin_bit_cast(bf16x8, b_fragment(zs[i], 32 * st, nt * 16, lane));
+          for (int i = 0; i < NS; ++i)
+            bp[i] = __builtin_bit_cast(bf16x8, b_fragment(zs[grp][i], 32 * st, nt * 16, lane));
 #pragma unroll
           for (int i = 0; i < NS; ++i)
 #pragma unroll
@@ -255,7 +264,7 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
     }
     __syncthreads();
     if (more) {
-      stage_store<NS, KS>(zs, tid, sr);
+      stage_store<NS, KS>(zs[grp], gtid, sr);
 #pragma unroll
       for (int st = 0; st < KS / 32; ++st) {
         ar[st][0] = an[st][0];
@@ -264,14 +273,34 @@ __global__ __launch_bounds__(kWaves * 64) void k_mm(MMArgs a, double alpha, doub
       __syncthreads();
     }
   }
+  if (G2 > 1) {
+    // groups 1.. hand their sums to group 0 through LDS (the rows are no
+    // longer read: every group passed the barrier after its last MFMAs)
+    float* red = reinterpret_cast<float*>(&zs[0][0][0][0]);
+    for (int g = 1; g < G2; ++g) {
+      if (grp == g && work)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) red[(gw * 64 + lane) * 16 + nt * 4 + i] = acc[nt][i];
+      __syncthreads();
+      if (grp == 0 && work)
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[nt][i] += red[(gw * 64 + lane) * 16 + nt * 4 + i];
+      __syncthreads();
+    }
+    if (grp != 0) return;
+  }
   if (!work) return;
-  // write: lane holds outputs ob + 16 wave + 4 lk + [0, 4), member 16 nt + lm
+  // write: lane holds outputs ob + 16 gw + 4 lk + [0, 4), member 16 nt + lm
 #pragma unroll
   for (int nt = 0; nt < 4; ++nt) {
     const int r = nt * 16 + lm;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int oo = ob + wave * 16 + 4 * lk + i;
+      const int oo = ob + gw * 16 + 4 * lk + i;
       if (oo >= u.nout) continue;
       const float v = acc[nt][i];
       if (PHASE == 1) {
@@ -296,14 +325,24 @@ hipError_t launch_ns(const MMArgs& a, double alpha, double beta, hipStream_t s, 
   if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL((k_split_members<NS>), dim3((unsigned)((n * kNR + 255) / 256)), dim3(256), 0, s, n, a.nrhs, a.X,
                      a.ldx, a.perm, static_cast<__bf16*>(a.Xs));
+  const dim3 g1((unsigned)a.ns1), g2((unsigned)a.n2);
+  const bool two1 = a.groups1 == 2, two2 = a.groups2 == 2;
   if (a.ns1 > 0) {
-    if (NS == 3 && a.ns1 >= kManySlices * a.cus)
-      hipLaunchKernelGGL((k_mm<NS, 1, 32>), dim3(a.ns1), dim3(kWaves * 64), 0, s, a, alpha, beta);
-    else
-      hipLaunchKernelGGL((k_mm<NS, 1, 64>), dim3(a.ns1), dim3(kWaves * 64), 0, s, a, alpha, beta);
+    if (NS == 3 && a.ns1 >= kManySlices * a.cus) {
+      if (two1) hipLaunchKernelGGL((k_mm<NS, 1, 32, 2>), g1, dim3(2 * kWaves * 64), 0, s, a, alpha, beta);
+      else hipLaunchKernelGGL((k_mm<NS, 1, 32, 1>), g1, dim3(kWaves * 64), 0, s, a, alpha, beta);
+    } else if (two1) {
+      hipLaunchKernelGGL((k_mm<NS, 1, 64, 2>), g1, dim3(2 * kWaves * 64), 0, s, a, alpha, beta);
+    } else {
+      hipLaunchKernelGGL((k_mm<NS, 1, 64, 1>), g1, dim3(kWaves * 64), 0, s, a, alpha, beta);
+    }
   }
   if (ev) (void)hipEventRecord(ev[1], s);
-  if (a.n2 > 0) hipLaunchKernelGGL((k_mm<NS, 2, NS == 3 ? 32 : 64>), dim3(a.n2), dim3(kWaves * 64), 0, s, a, alpha, beta);
+  if (a.n2 > 0) {
+    constexpr int KS2 = NS == 3 ? 32 : 64;
+    if (two2) hipLaunchKernelGGL((k_mm<NS, 2, KS2, 2>), g2, dim3(2 * kWaves * 64), 0, s, a, alpha, beta);
+    else hipLaunchKernelGGL((k_mm<NS, 2, KS2, 1>), g2, dim3(kWaves * 64), 0, s, a, alpha, beta);
+  }
   if (ev) (void)hipEventRecord(ev[2], s);
   return hipGetLastError();
 }

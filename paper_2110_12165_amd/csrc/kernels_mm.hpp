@@ -25,6 +25,7 @@ struct MMArgs {
   int64_t ldy;
   int32_t nrhs;            // 1..64
   int32_t cus;             // compute units of the device
+  int32_t groups1, groups2;  // wave groups (1 or 2) sharing a 64-output slice in phase 1, phase 2
 };
 
 // parts = 2 (3 bf16 products, "BF16x3") or 3 (6 products, "BF16x6").

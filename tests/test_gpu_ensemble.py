@@ -21,20 +21,35 @@ from synth.faults import MU, NU
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=["dip30_150x70", "planar64x32"])
+_oracles = {}
+
+
+# (workload, wave groups per slice: 0 = timed choice, 1 or 2 forced)
+@pytest.fixture(scope="module", params=[("dip30_150x70", 0), ("dip30_150x70", 1), ("dip30_150x70", 2),
+                                        ("planar64x32", 1), ("planar64x32", 2)],
+                ids=lambda p: f"{p[0]}-g{p[1]}")
 def case(request):
     import torch
 
     import paper_2110_12165_amd as hm
-    name = request.param
+    name, groups = request.param
     w = WORKLOADS[name]
     f = config_fault(name)
-    g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
-    H = OracleH.build(g, w["leaf"], w["eta"], w["aca_eps"], w["lattice"])
-    B = oracle_blocks(H)
+    if name not in _oracles:
+        g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
+        H = OracleH.build(g, w["leaf"], w["eta"], w["aca_eps"], w["lattice"])
+        _oracles[name] = (H, oracle_blocks(H))
+    H, B = _oracles[name]
     Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec="f32", kernel="split",
-                                wg_waves=8, wg_waves_p1=4, max_nrhs=64)
-    return torch, hm, name, f, H, Hg
+                                wg_waves=8, wg_waves_p1=4, max_nrhs=64, mm_groups=groups)
+    mg = Hg.info()["mm_groups"]
+    say(f"[ensemble] {name} wave groups {mg}")
+    if groups:
+        assert mg == {"x3": (groups, groups), "x6": (groups, groups)}
+    else:
+        assert all(v in (1, 2) for m in mg.values() for v in m)
+    yield torch, hm, f"{name}-g{groups}", f, H, Hg
+    Hg.close()
 
 
 @pytest.mark.parametrize("mode,tol", [("x6", 2e-5), ("x3", 1e-3)])

@@ -61,6 +61,27 @@ def test_full_size_against_exact_product(setup, variant):
     assert info["max_rank"] <= 64 and info["n_lr"] > 40000
 
 
+@pytest.mark.parametrize("groups", [1, 2])
+def test_full_size_ensemble_against_exact_product(setup, groups):
+    """The ensemble product (BF16x6 and BF16x3 on MFMA) with one and with
+    two wave groups per 64-output slice, against exact products."""
+    torch, hm, bench_options, w, f, x, y_exact = setup
+    opts = dict(bench_options(NAME, "batched_f32"), max_nrhs=64, mm_groups=groups)
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, **opts)
+    dev = torch.device("cuda:0")
+    X = loguniform_rates(f.n, 3, nrhs=4)
+    ref = np.stack([fft_grid_product(f.nx, f.ny, f.h, f.slip, MU, NU, X[:, c]) for c in range(4)], axis=1)
+    Xd = torch.tensor(X, device=dev)
+    Y6 = H.matmat(Xd, mode="x6").cpu().numpy()
+    Y3 = H.matmat(Xd, mode="x3").cpu().numpy()
+    info = H.info()
+    H.close()
+    r6, r3 = rel(Y6, ref), rel(Y3, ref)
+    say(f"[full] {NAME} ensemble groups {groups}: rel x6 {r6:.3e} x3 {r3:.3e}")
+    assert info["mm_groups"] == {"x3": (groups, groups), "x6": (groups, groups)}
+    assert r6 <= 2e-5 and r3 <= 1e-3
+
+
 def test_aca_tolerance_controls_the_product_error():
     """The ACA tolerance of eq. (19) sets the product's error: at N = 30720
     (the benchmark fault at a quarter of its size) and eps from 1e-3 to
