@@ -186,10 +186,10 @@ __device__ __forceinline__ void load_a(const float* pool, const Unit& u, int c0,
 // G2 groups of four waves share a slice: group g takes rounds g, g + G2, ...
 // into its own LDS rows, and the groups' sums are added in group order at
 // the end.  G2 = 2 halves the path of every workgroup and the workgroups
-// resident per compute unit; the caller chooses per phase.  Rounds are software-pipelined:
-// the members and panel quads of a group's next round are loaded into
-// registers while the MFMAs of its current round run, and written to LDS
-// after it.
+// resident per compute unit; the caller chooses per phase (MMArgs groups).
+// Rounds are software-pipelined: the members and panel quads of a group's
+// next round are loaded into registers while the MFMAs of its current round
+// run, and written to LDS after it.
 template <int NS, int PHASE, int KS, int G2>
 __global__ __launch_bounds__(kWaves * 64 * G2) void k_mm(MMArgs a, double alpha, double beta) {
   __bf16* Ts = static_cast<__bf16*>(a.Ts);
