@@ -78,19 +78,38 @@ __device__ __forceinline__ void split(float x, __bf16* p) {
 }
 
 // Member values of the inputs, split: Xs[p][k][r] (cluster order k < n).
-template <int NS>
+// One thread per input and four members (8-byte stores per part); VEC: X and
+// ldx allow 16-byte loads.
+template <int NS, bool VEC>
 __global__ __launch_bounds__(256) void k_split_members(int64_t n, int nrhs, const double* __restrict__ X,
                                                        int64_t ldx, const int32_t* __restrict__ perm,
                                                        __bf16* __restrict__ Xs) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (k, r)
-  if (e >= n * kNR) return;
-  const int64_t k = e / kNR;
-  const int r = (int)(e % kNR);
-  const float v = r < nrhs ? (float)X[(int64_t)perm[k] * ldx + r] : 0.f;
-  __bf16 p[NS];
-  split<NS>(v, p);
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // (k, members 4 j + [0, 4))
+  if (e >= n * (kNR / 4)) return;
+  const int64_t k = e / (kNR / 4);
+  const int r0 = 4 * (int)(e % (kNR / 4));
+  const double* xr = X + (int64_t)perm[k] * ldx + r0;
+  float v[4];
+  if (VEC && r0 + 4 <= nrhs) {
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const f64x2 a = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(xr));
+    const f64x2 b = __builtin_nontemporal_load(reinterpret_cast<const f64x2*>(xr) + 1);
+    v[0] = (float)a[0];
+    v[1] = (float)a[1];
+    v[2] = (float)b[0];
+    v[3] = (float)b[1];
+  } else {
 #pragma unroll
-  for (int i = 0; i < NS; ++i) Xs[((int64_t)i * n + k) * kNR + r] = p[i];
+    for (int j = 0; j < 4; ++j) v[j] = r0 + j < nrhs ? (float)xr[j] : 0.f;
+  }
+  __bf16 p[4][NS];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) split<NS>(v[j], p[j]);
+#pragma unroll
+  for (int i = 0; i < NS; ++i) {
+    typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+    *reinterpret_cast<bf16x4*>(Xs + ((int64_t)i * n + k) * kNR + r0) = bf16x4{p[0][i], p[1][i], p[2][i], p[3][i]};
+  }
 }
 
 // 16-byte staging items per thread and part
@@ -323,8 +342,13 @@ template <int NS>
 hipError_t launch_ns(const MMArgs& a, double alpha, double beta, hipStream_t s, hipEvent_t* ev) {
   const int64_t n = a.n;
   if (ev) (void)hipEventRecord(ev[0], s);
-  hipLaunchKernelGGL((k_split_members<NS>), dim3((unsigned)((n * kNR + 255) / 256)), dim3(256), 0, s, n, a.nrhs, a.X,
-                     a.ldx, a.perm, static_cast<__bf16*>(a.Xs));
+  const dim3 gs((unsigned)((n * (kNR / 4) + 255) / 256));
+  if (reinterpret_cast<uintptr_t>(a.X) % 16 == 0 && a.ldx % 2 == 0)
+    hipLaunchKernelGGL((k_split_members<NS, true>), gs, dim3(256), 0, s, n, a.nrhs, a.X, a.ldx, a.perm,
+                       static_cast<__bf16*>(a.Xs));
+  else
+    hipLaunchKernelGGL((k_split_members<NS, false>), gs, dim3(256), 0, s, n, a.nrhs, a.X, a.ldx, a.perm,
+                       static_cast<__bf16*>(a.Xs));
   const dim3 g1((unsigned)a.ns1), g2((unsigned)a.n2);
   const bool two1 = a.groups1 == 2, two2 = a.groups2 == 2;
   if (a.ns1 > 0) {
