@@ -255,7 +255,10 @@ hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, in
  *     ldx, ldy >= nrhs; X and Y must not overlap.  Members are processed in
  *     groups of 64.
  *   Requires a handle created with max_nrhs > 0 (HMAT_ESTATE otherwise).
- *   Allocates nothing and does not wait for the GPU.
+ *   Allocates nothing and does not wait for the GPU.  Results are
+ *   reproducible for a handle; the wave-group choice (hmat_opts.mm_groups)
+ *   sets the order of the FP32 sums, so two handles whose timed choices
+ *   differ agree to rounding only (fix mm_groups for identical results).
  */
 hmat_status hmat_matmat(hmat_t h, const double* X, int64_t ldx, double* Y, int64_t ldy, int64_t nrhs, double alpha,
                         double beta, int32_t mode, void* stream);
