@@ -87,3 +87,35 @@ def test_ensemble_matches_single_vector_products(case):
     Ym = Hg.matmat(X, mode="x6").cpu().numpy()
     Yv = np.stack([Hg.matvec(X[:, c].contiguous()).cpu().numpy() for c in range(16)], axis=1)
     assert rel(Ym, Yv) <= 2e-5
+
+
+@pytest.mark.parametrize("groups", [0, 1, 2])
+def test_ensemble_degenerate_sizes(groups):
+    """Tiny meshes (one element, no low-rank block, a single leaf) and a
+    matrix of zeros (the normal component of a planar fault): the ensemble
+    product against the dense oracle matrix, and beta * Y kept."""
+    import torch
+
+    import paper_2110_12165_amd as hm
+    from oracle.dense import dense_matrix
+    from synth import planar_rect_fault
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(17)
+    for nx, ny, leaf in ((1, 1, 4), (2, 1, 4), (3, 2, 1), (5, 3, 64)):
+        f = planar_rect_fault(nx, ny, 100.0, 90.0, "strike")
+        A = dense_matrix(CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU))
+        Hg = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, leaf=leaf, prec="f32", kernel="split", max_nrhs=64,
+                              mm_groups=groups)
+        X = rng.standard_normal((f.n, 3))
+        for mode, tol in (("x6", 2e-5), ("x3", 1e-3)):
+            Y = Hg.matmat(torch.tensor(X, device=dev), mode=mode).cpu().numpy()
+            assert rel(Y, A @ X) <= tol, (nx, ny, leaf, mode)
+        Hg.close()
+    f = planar_rect_fault(16, 8, 100.0, 90.0, "strike")
+    Hb = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=1, leaf=8, lattice=2, prec="f32", kernel="split",
+                          max_nrhs=64, mm_groups=groups)
+    Y0 = torch.tensor(rng.standard_normal((f.n, 5)), device=dev)
+    Y = Y0.clone()
+    Hb.matmat(torch.ones((f.n, 5), dtype=torch.float64, device=dev), Y=Y, alpha=1.0, beta=2.0, mode="x6")
+    assert torch.equal(Y, 2.0 * Y0)
+    Hb.close()
