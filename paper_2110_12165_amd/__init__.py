@@ -39,6 +39,16 @@ def _dptr(t):
     return C.c_void_p(t.data_ptr())
 
 
+def _gpu_f64(t, shape, name, contiguous=True):
+    """Raise unless t is a float64 GPU tensor of the given shape (and
+    contiguous): its address goes to the device kernels unchecked."""
+    torch = _torch()
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and tuple(t.shape) == tuple(shape) and (t.is_contiguous() or not contiguous)):
+        raise ValueError(f"{name} must be a {'contiguous ' if contiguous else ''}float64 GPU tensor of shape "
+                         f"{tuple(shape)}")
+
+
 class HMatrix:
     """Handle on a lattice H-matrix held on the current GPU."""
 
@@ -114,13 +124,14 @@ class HMatrix:
                 raise ValueError("x has the wrong length")
             xc = x.contiguous()
             out = torch.empty_like(xc) if y is None else y
-            if out.shape != xc.shape or not out.is_contiguous() or out.dtype != torch.float64:
-                raise ValueError("y must be a contiguous float64 tensor shaped like x")
+            _gpu_f64(out, (n,), "y")
             check(fn(self._h, _dptr(xc), _dptr(out), 1, n, alpha, 0.0 if y is None else beta, _stream_ptr(stream)))
             return out
         if x.dim() != 2 or x.shape[0] != n:
             raise ValueError("x must be (n,) or (n, k)")
         k = x.shape[1]
+        if y is not None:
+            _gpu_f64(y, (n, k), "y", contiguous=False)
         xt = x.t().contiguous()                       # (k, n): column-major n x k, ld = n
         yt = torch.empty_like(xt) if y is None else y.t().contiguous()
         check(fn(self._h, _dptr(xt), _dptr(yt), k, n, alpha, 0.0 if y is None else beta, _stream_ptr(stream)))
@@ -147,8 +158,7 @@ class HMatrix:
             raise ValueError("X must be a float64 GPU tensor of shape (n, k)")
         Xc = X.contiguous()
         out = torch.empty_like(Xc) if Y is None else Y
-        if out.shape != Xc.shape or not out.is_contiguous() or out.dtype != torch.float64:
-            raise ValueError("Y must be a contiguous float64 tensor shaped like X")
+        _gpu_f64(out, Xc.shape, "Y")
         k = Xc.shape[1]
         check(self._lib.hmat_matmat(self._h, _dptr(Xc), k, _dptr(out), k, k, alpha, 0.0 if Y is None else beta,
                                     _lib.MM_MODE[mode], _stream_ptr(stream)))
@@ -190,6 +200,8 @@ class HMatrix:
 
     def profile(self, x, y, reps=50, stream=None):
         """hmat_profile: per-launch mean durations (ms) and algorithmic bytes."""
+        _gpu_f64(x, (self.n,), "x")
+        _gpu_f64(y, (self.n,), "y")
         pr = _lib.HmatProfile()
         check(self._lib.hmat_profile(self._h, _dptr(x), _dptr(y), reps, _stream_ptr(stream), C.byref(pr)))
         nl = pr.n_launches
@@ -218,11 +230,13 @@ def rs_rhs(A: HMatrix, B, y, a, b, dc, V0, f0, eta_rad, V_pl, dydt=None, V_out=N
     n = A.n
     if y.shape != (3 * n,) or y.dtype != torch.float64 or not y.is_cuda:
         raise ValueError("y must be a float64 GPU tensor of length 3n")
-    for t in (a, b, dc):
-        if t.shape != (n,) or t.dtype != torch.float64 or not t.is_cuda:
-            raise ValueError("a, b, dc must be float64 GPU tensors of length n")
+    for t, name in ((a, "a"), (b, "b"), (dc, "dc")):
+        _gpu_f64(t, (n,), name)
     y = y.contiguous()
     out = torch.empty_like(y) if dydt is None else dydt
+    _gpu_f64(out, (3 * n,), "dydt")
+    if V_out is not None:
+        _gpu_f64(V_out, (n,), "V_out")
     p = _lib.RsParams(n, V0, f0, eta_rad, V_pl, a.data_ptr(), b.data_ptr(), dc.data_ptr())
     lib = _lib.load()
     check(lib.rs_rhs(A._h, None if B is None else B._h, C.byref(p), _dptr(y), _dptr(out),
@@ -241,9 +255,8 @@ class RK45:
         torch = _torch()
         self.A, self.B = A, B
         n = A.n
-        for t in (a, b, dc):
-            if t.shape != (n,) or t.dtype != torch.float64 or not t.is_cuda:
-                raise ValueError("a, b, dc must be float64 GPU tensors of length n")
+        for t, name in ((a, "a"), (b, "b"), (dc, "dc")):
+            _gpu_f64(t, (n,), name)
         self._keep = (a, b, dc)
         self.params = _lib.RsParams(n, V0, f0, eta_rad, V_pl, a.data_ptr(), b.data_ptr(), dc.data_ptr())
         nbytes = _lib.load().rs_rk45_workspace_bytes(n)
@@ -251,12 +264,9 @@ class RK45:
         self.state = _lib.RsRk45State(0.0, dt0, eps_rk, 0.0, 0, 0)
 
     def _check(self, y, D):
-        torch = _torch()
         n = self.A.n
-        if y.shape != (3 * n,) or D.shape != (n,) or y.dtype != torch.float64 or D.dtype != torch.float64:
-            raise ValueError("y must be (3n,) and D (n,) float64 GPU tensors")
-        if not (y.is_contiguous() and D.is_contiguous()):
-            raise ValueError("y and D must be contiguous")
+        _gpu_f64(y, (3 * n,), "y")
+        _gpu_f64(D, (n,), "D")
 
     def attempt(self, y, D, force=-1, stream=None):
         self._check(y, D)
@@ -294,10 +304,9 @@ class RK45:
         checkpoints (the state before every ckpt_every-th step) for adjoint()."""
         torch = _torch()
         n = self.A.n
-        if y.shape != (3 * n,) or y.dtype != torch.float64 or not y.is_contiguous():
-            raise ValueError("y must be a contiguous (3n,) float64 GPU tensor")
-        if D is not None and (D.shape != (n,) or D.dtype != torch.float64 or not D.is_contiguous()):
-            raise ValueError("D must be a contiguous (n,) float64 GPU tensor")
+        _gpu_f64(y, (3 * n,), "y")
+        if D is not None:
+            _gpu_f64(D, (n,), "D")
         d = np.ascontiguousarray(dts, dtype=np.float64)
         m = d.shape[0]
         ckpt = None
@@ -324,9 +333,11 @@ class RK45:
             a_bar = torch.zeros(n, dtype=torch.float64, device=dev)
         if dc_bar is None:
             dc_bar = torch.zeros(n, dtype=torch.float64, device=dev)
-        for t, k in ((y_bar, 3 * n), (a_bar, n), (dc_bar, n)) + (() if D_bar is None else ((D_bar, n),)):
-            if t.shape != (k,) or t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
-                raise ValueError("cotangents must be contiguous float64 GPU tensors of length 3n (state) or n")
+        for t, k, name in ((y_bar, 3 * n, "y_bar"), (a_bar, n, "a_bar"), (dc_bar, n, "dc_bar")) + (
+                () if D_bar is None else ((D_bar, n, "D_bar"),)):
+            _gpu_f64(t, (k,), name)
+        if ckpt is not None and ckpt_every > 0:
+            _gpu_f64(ckpt, (((m + ckpt_every - 1) // ckpt_every) * 3 * n,), "ckpt")
         lib = _lib.load()
         nbytes = lib.rs_rk45_adjoint_workspace_bytes(n, max(1, min(ckpt_every, m)))
         if nbytes < 0:
@@ -386,12 +397,9 @@ class EnsembleRK45:
     def run(self, y, D, n_accept, max_attempts=0, use_graph=True, stream=None):
         """Advance every member by n_accept accepted steps (graph replay needs
         a non-default stream)."""
-        torch = _torch()
         n, m = self.A.n, self.members
-        if y.shape != (3, n, m) or D.shape != (n, m) or y.dtype != torch.float64 or D.dtype != torch.float64:
-            raise ValueError("y must be (3, n, members) and D (n, members) float64 GPU tensors")
-        if not (y.is_contiguous() and D.is_contiguous()):
-            raise ValueError("y and D must be contiguous")
+        _gpu_f64(y, (3, n, m), "y")
+        _gpu_f64(D, (n, m), "D")
         check(_lib.load().rs_ens_rk45_run(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
                                           _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state), n_accept,
                                           max_attempts, 1 if use_graph else 0, _stream_ptr(stream)))

@@ -247,3 +247,47 @@ def test_row_split_layouts(torch_dev, hm, wg, wg1):
             assert rel(yw, ref) <= tol
             if wg1 == 4:
                 assert n_split > n_whole   # the layout did split units
+
+
+def test_binding_rejects_host_and_misshaped_tensors(torch_dev, hm):
+    """Tensors whose addresses would reach the kernels unchecked (outputs on
+    the host, wrong shapes, non-contiguous views) are refused by the binding
+    before any launch."""
+    torch, dev = torch_dev
+    from synth import planar_rect_fault
+    f = planar_rect_fault(8, 4, 100.0, 90.0, "strike")
+    n = f.n
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, leaf=4, prec="f32", kernel="split", max_nrhs=8)
+    x = torch.ones(n, dtype=torch.float64, device=dev)
+    X = torch.ones((n, 3), dtype=torch.float64, device=dev)
+    bad_y = (torch.empty(n, dtype=torch.float64), torch.empty(n + 1, dtype=torch.float64, device=dev),
+             torch.empty(n, dtype=torch.float32, device=dev), torch.empty(2 * n, dtype=torch.float64, device=dev)[::2])
+    for y in bad_y:
+        with pytest.raises(ValueError):
+            H.matvec(x, y=y)
+        with pytest.raises(ValueError):
+            H.profile(x, y, reps=1)
+    with pytest.raises(ValueError):
+        H.matvec(X, y=torch.empty((n, 2), dtype=torch.float64, device=dev))
+    with pytest.raises(ValueError):
+        H.matvec(X, y=torch.empty((n, 3), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        H.matmat(X, Y=torch.empty((n, 3), dtype=torch.float64))
+    with pytest.raises(ValueError):
+        H.matmat(X, Y=torch.empty((3, n), dtype=torch.float64, device=dev).t())
+    a = torch.full((n,), 0.01, dtype=torch.float64, device=dev)
+    strided = torch.full((2 * n,), 0.01, dtype=torch.float64, device=dev)[::2]
+    with pytest.raises(ValueError):
+        hm.RK45(H, None, strided, a, a, 1e-6, 0.6, 4.6e6, 1e-9)
+    rk = hm.RK45(H, None, a, a, a, 1e-6, 0.6, 4.6e6, 1e-9)
+    y = torch.ones(3 * n, dtype=torch.float64, device=dev)
+    with pytest.raises(ValueError):
+        rk.run(y, torch.zeros(n, dtype=torch.float64), 1)
+    with pytest.raises(ValueError):
+        hm.rs_rhs(H, None, y, a, a, a, 1e-6, 0.6, 4.6e6, 1e-9, dydt=torch.empty(3 * n, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        hm.rs_rhs(H, None, y, a, a, a, 1e-6, 0.6, 4.6e6, 1e-9, V_out=torch.empty(n + 1, dtype=torch.float64,
+                                                                                      device=dev))
+    # the valid calls still run
+    assert H.matvec(x).shape == (n,) and H.matmat(X).shape == (n, 3)
+    H.close()
