@@ -214,17 +214,18 @@ def ensemble(torch, hm, workloads, reps=20):
     """64-member ensemble product on MFMA (hmat_matmat, BF16x6 and BF16x3)
     against 64 single-vector FP32 batched products on the same handle."""
     from paper_2110_12165_amd.tuning import bench_options
-    from synth import WORKLOADS, config_fault, loguniform_rates
+    from synth import TRIANGLE_WORKLOADS, WORKLOADS, config_fault, config_triangle_fault, loguniform_rates
     from synth.faults import MU, NU
 
     out = {}
     dev = torch.device("cuda:0")
     for name in workloads:
-        w = WORKLOADS[name]
-        f = config_fault(name)
+        tri = name in TRIANGLE_WORKLOADS
+        w = (TRIANGLE_WORKLOADS if tri else WORKLOADS)[name]
+        f = (config_triangle_fault if tri else config_fault)(name)
         opts = bench_options(name, "batched_f32") if name in ("dip30_480x256",) else dict(
             aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"], prec="f32",
-            kernel="split")
+            kernel="split", build_device=1)
         H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, max_nrhs=64, **opts)
         info = H.info()
         X = torch.tensor(loguniform_rates(f.n, 3, nrhs=64), device=dev)
@@ -255,7 +256,8 @@ def ensemble(torch, hm, workloads, reps=20):
         torch.cuda.empty_cache()
         r6 = float(np.linalg.norm(Y6 - Yv) / np.linalg.norm(Yv))
         r3 = float(np.linalg.norm(Y3 - Yv) / np.linalg.norm(Yv))
-        res = {"N": f.n, "members": 64, "factor_bytes": info["factor_bytes"],
+        res = {"N": f.n, "members": 64, "matrix": "A (shear)", "factor_bytes": info["factor_bytes"],
+               "wave_groups": info["mm_groups"],
                "ms_mfma_bf16x6": ms_x6, "ms_mfma_bf16x3": ms_x3, "ms_64_fp32_matvecs": ms_vec,
                "speedup_x6_vs_64_matvecs": ms_vec / ms_x6, "speedup_x3_vs_64_matvecs": ms_vec / ms_x3,
                "member_products_per_s_x6": 64e3 / ms_x6,
@@ -269,22 +271,25 @@ def ensemble(torch, hm, workloads, reps=20):
     return out
 
 
-def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4):
-    """64 rate-and-state simulations on the N = 21000 mesh advanced together
+def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4, name="thrust_150x70"):
+    """64 rate-and-state simulations on one N = 21000 fault advanced together
     (rs_ens_rk45_run: per-member FP64 state and step control, one BF16x3 MFMA
-    ensemble product per stage), against single simulations with the FP32
-    single-vector product (rs_rk45_run), n_single of them timed and the time
-    scaled to all members."""
-    from synth import WORKLOADS, config_fault, ensemble_params
+    ensemble product per matrix and stage), against single simulations with
+    the FP32 single-vector products (rs_rk45_run), n_single of them timed and
+    the time scaled to all members.  On the curved thrust fault (triangles)
+    the normal stress evolves too: products with A and B."""
+    from synth import TRIANGLE_WORKLOADS, WORKLOADS, config_fault, config_triangle_fault, ensemble_params
     from synth.faults import MU, NU
 
-    name = "dip30_150x140"
-    w = WORKLOADS[name]
-    f = config_fault(name)
+    tri = name in TRIANGLE_WORKLOADS
+    w = (TRIANGLE_WORKLOADS if tri else WORKLOADS)[name]
+    f = (config_triangle_fault if tri else config_fault)(name)
     n = f.n
     dev = torch.device("cuda:0")
-    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
-                         lattice=w["lattice"], prec="f32", kernel="split", max_nrhs=64)
+    opts = dict(aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"], prec="f32",
+                kernel="split", max_nrhs=64, build_device=1, transpose=0)
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=0, **opts)
+    HB = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=1, **opts) if tri else None
     p = ensemble_params(f, members, 3)
     V = 10.0 ** (-12.0 + 3.0 * np.random.default_rng(5).random((n, members)))
     phi = p["f0"] + p["b"] * np.log(p["V0"] / V)
@@ -294,7 +299,7 @@ def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4):
     a, b, dc = (torch.tensor(np.ascontiguousarray(p[k]), device=dev) for k in ("a", "b", "dc"))
     consts = (p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
     s = torch.cuda.Stream()
-    ens = hm.EnsembleRK45(H, None, a, b, dc, *consts, mode=mode)
+    ens = hm.EnsembleRK45(H, HB, a, b, dc, *consts, mode=mode)
     y = torch.tensor(y0, device=dev)
     D = torch.zeros((n, members), dtype=torch.float64, device=dev)
     with torch.cuda.stream(s):
@@ -311,7 +316,7 @@ def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4):
     single_attempts = 0
     for r in range(n_single):
         ar, br, dcr = (t[:, r].contiguous() for t in (a, b, dc))
-        rk = hm.RK45(H, None, ar, br, dcr, *consts)
+        rk = hm.RK45(H, HB, ar, br, dcr, *consts)
         yr = torch.tensor(np.ascontiguousarray(y0[:, :, r].reshape(-1)), device=dev)
         Dr = torch.zeros(n, dtype=torch.float64, device=dev)
         with torch.cuda.stream(s):
@@ -324,16 +329,22 @@ def ensemble_rk(torch, hm, n_steps, members=64, mode="x3", n_single=4):
             single += time.perf_counter() - t1
         single_attempts += rk.state.accepted + rk.state.rejected - a0
     single_all = single / n_single * members
+    sig_moved = float((y[2] - torch.tensor(y0[2], device=dev)).abs().max())
     H.close()
+    if HB is not None:
+        HB.close()
     torch.cuda.empty_cache()
-    log(f"[bench] ensemble rk45: {members} members x {n_steps} steps in {wall:.3f} s ({attempts} attempts); "
+    log(f"[bench] ensemble rk45 {name} ({'A and B' if tri else 'A'}): {members} members x {n_steps} steps in "
+        f"{wall:.3f} s ({attempts} attempts); "
         f"single simulations {single / n_single:.3f} s each -> {single_all:.3f} s for {members} (x{single_all / wall:.1f})")
-    return {"workload": name, "N": n, "members": members, "mode": mode, "steps_per_member": n_steps,
+    return {"workload": name, "N": n, "matrices": "A and B" if tri else "A", "members": members, "mode": mode,
+            "steps_per_member": n_steps,
             "attempts": attempts, "wall_s": wall, "member_steps_per_s": members * n_steps / wall,
             "single_wall_s_each": single / n_single, "single_attempts_mean": single_attempts / n_single,
-            "speedup_vs_single_runs": single_all / wall,
+            "speedup_vs_single_runs": single_all / wall, "sigma_change_max_pa": sig_moved,
             "note": "per-element a - b ~ U[-0.006, 0.004] (b = 0.015), d_c log-uniform [0.005, 0.05] m (seed 3); "
-                    "graph-replayed attempts; single runs use the FP32 single-vector product"}
+                    + ("sigma 20-120 MPa rising with depth; " if tri else "sigma 50 MPa; ")
+                    + "graph-replayed attempts; single runs use the FP32 single-vector products"}
 
 
 def nonplanar(torch, hm, reps=50, rk_steps=500):
@@ -534,25 +545,31 @@ def sweeps(torch, hm, steps=50, warmup=5):
     return out
 
 
-def adjoint_run(torch, hm, n_steps, ckpt_every=50):
+def adjoint_run(torch, hm, n_steps, ckpt_every=50, name="thrust_150x70"):
     """Gradient of the final-slip misfit L = 1/2 |D_M - D_target|^2 for
-    per-element a (b fixed) and d_c on the N = 21000 mesh with FP32 factors:
+    per-element a (b fixed) and d_c on an N = 21000 fault with FP32 factors:
     a controlled run logs its n_steps accepted steps; the target slip comes
     from a perturbed by U(-1e-3, 1e-3) (seed 4), integrated with its own step
     control to the same final time; then the timed part: the frozen-step
     replay writing checkpoints every ckpt_every steps, and the adjoint sweep
-    (segments recomputed from their checkpoints, one A^T product per stage)."""
-    from synth import WORKLOADS, config_fault, friction_params
+    (segments recomputed from their checkpoints, one transposed product per
+    matrix and stage).  On the curved thrust fault (triangles) both A and B
+    enter (shear and normal stress)."""
+    from synth import (TRIANGLE_WORKLOADS, WORKLOADS, config_fault, config_triangle_fault, friction_params,
+                       triangle_friction_params)
     from synth.faults import MU, NU
 
-    name = "dip30_150x140"
-    w = WORKLOADS[name]
-    f = config_fault(name)
-    p = friction_params(f)
+    tri = name in TRIANGLE_WORKLOADS
+    w = (TRIANGLE_WORKLOADS if tri else WORKLOADS)[name]
+    f = (config_triangle_fault if tri else config_fault)(name)
+    p = (triangle_friction_params if tri else friction_params)(f)
     n = f.n
     dev = torch.device("cuda:0")
-    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
-                         lattice=w["lattice"], prec="f32", kernel="split")
+    opts = dict(aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"], lattice=w["lattice"], prec="f32",
+                kernel="split", build_device=1)
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=0, **opts)
+    HB = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=1, **opts) if tri else None
+    mats = [H] + ([HB] if tri else [])
     a, b, dc = (torch.tensor(p[k], device=dev) for k in ("a", "b", "dc"))
     # steady state at log-uniform slip rates (seed 3), then the state variable kicked by U(-0.05, 0.05)
     V = 10.0 ** (-12.0 + 3.0 * np.random.default_rng(3).random(n))
@@ -561,7 +578,7 @@ def adjoint_run(torch, hm, n_steps, ckpt_every=50):
     phi = phi + np.random.default_rng(103).uniform(-0.05, 0.05, n)
     y0 = np.concatenate([phi, tau, p["sigma"]])
     consts = (p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
-    rk = hm.RK45(H, None, a, b, dc, *consts)
+    rk = hm.RK45(H, HB, a, b, dc, *consts)
     y = torch.tensor(y0, device=dev)
     D = torch.zeros(n, dtype=torch.float64, device=dev)
     log_dt = torch.zeros(n_steps, dtype=torch.float64, device=dev)
@@ -569,7 +586,7 @@ def adjoint_run(torch, hm, n_steps, ckpt_every=50):
     dts = log_dt.cpu().numpy()
     T = rk.t
     at = a + torch.tensor(np.random.default_rng(4).uniform(-1e-3, 1e-3, n), device=dev)
-    rkt = hm.RK45(H, None, at, b, dc, *consts)
+    rkt = hm.RK45(H, HB, at, b, dc, *consts)
     yt = torch.tensor(y0, device=dev)
     D_t = torch.zeros(n, dtype=torch.float64, device=dev)
     while rkt.t + rkt.dt < T:
@@ -594,31 +611,36 @@ def adjoint_run(torch, hm, n_steps, ckpt_every=50):
     t2 = time.perf_counter()
     x = torch.tensor(V, device=dev)
     yv = torch.empty_like(x)
-    prof = H.profile(x, yv, reps=20)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for _ in range(3):
-        H.matvec_T(x, y=yv)
-    e0.record()
-    for _ in range(20):
-        H.matvec_T(x, y=yv)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_t = e0.elapsed_time(e1) / 20
+    ms_f, ms_t = 0.0, 0.0   # one product with each matrix, and with each transpose
+    for M in mats:
+        ms_f += M.profile(x, yv, reps=20)["ms_product"]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for _ in range(3):
+            M.matvec_T(x, y=yv)
+        e0.record()
+        for _ in range(20):
+            M.matvec_T(x, y=yv)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_t += e0.elapsed_time(e1) / 20
     fwd, bwd = t1 - t0, t2 - t1
-    prod_s = (12 * n_steps * prof["ms_product"] + 6 * n_steps * ms_t) * 1e-3
-    H.close()
+    prod_s = (12 * n_steps * ms_f + 6 * n_steps * ms_t) * 1e-3
+    for M in mats:
+        M.close()
     torch.cuda.empty_cache()
     loss = 0.5 * float((Dbar * Dbar).sum())
-    log(f"[bench] adjoint: N={n}, {n_steps} steps to t={T:.3e} s, forward {fwd:.3f} s, adjoint {bwd:.3f} s, "
-        f"L={loss:.3e}")
-    return {"workload": name, "N": n, "steps": n_steps, "ckpt_every": ckpt_every, "factor_storage": "f32",
+    log(f"[bench] adjoint {name} ({'A and B' if tri else 'A'}): N={n}, {n_steps} steps to t={T:.3e} s, "
+        f"forward {fwd:.3f} s, adjoint {bwd:.3f} s, L={loss:.3e}")
+    return {"workload": name, "N": n, "matrices": "A and B" if tri else "A", "steps": n_steps,
+            "ckpt_every": ckpt_every, "factor_storage": "f32",
             "simulated_s": T, "forward_replay_s": fwd, "adjoint_s": bwd, "gradient_s": fwd + bwd,
-            "products": 18 * n_steps, "ms_product": prof["ms_product"], "ms_product_T": ms_t,
+            "products": 18 * n_steps * len(mats), "ms_products": ms_f, "ms_products_T": ms_t,
             "hmvm_share": prod_s / (fwd + bwd), "loss": loss,
             "grad_a_norm": float(ga.norm()), "grad_dc_norm": float(gdc.norm()),
             "note": "L = 1/2 |D_M - D_target|^2; D_target from a + U(-1e-3, 1e-3) (seed 4) by its own step control "
                     "to the same final time; gradient by the discrete adjoint of the frozen-step replay; "
-                    "products: 6 per step forward, 6 per step recomputed from checkpoints, 6 transposed"}
+                    "products per matrix: 6 per step forward, 6 per step recomputed from checkpoints, 6 transposed; "
+                    "ms_products(_T): one product with each matrix (its transpose), summed"}
 
 
 def main():
@@ -630,7 +652,7 @@ def main():
     ap.add_argument("--variants", default="batched_f32,plain_f64,batched_f64")
     ap.add_argument("--rk-steps", type=int, default=1000,
                     help="accepted RK45 steps of the rate-and-state simulation on the same fault (0: skip)")
-    ap.add_argument("--ensemble", default="dip30_150x140,dip30_480x256",
+    ap.add_argument("--ensemble", default="thrust_150x70,dip30_480x256",
                     help="workloads of the 64-member MFMA ensemble product ('' to skip)")
     ap.add_argument("--no-nonplanar", action="store_true", help="skip the triangle-mesh section")
     ap.add_argument("--no-construction", action="store_true", help="skip the host/device build timing")

@@ -158,18 +158,20 @@ def friction_params(f: PlanarRectFault) -> dict:
     )
 
 
-def ensemble_params(f: PlanarRectFault, members: int, seed: int) -> dict:
+def ensemble_params(f, members: int, seed: int) -> dict:
     """Per-member friction of the many-member runs: per element and member,
     a - b ~ U[-0.006, 0.004] with b = 0.015 fixed (a = b + (a - b)), and
     d_c log-uniform in [0.005, 0.05] m, from numpy's default_rng(seed).
-    Arrays are (n, members); sigma = 50 MPa and the constants as in
-    friction_params."""
+    Arrays are (n, members); sigma = 50 MPa on a planar fault and the depth
+    profile of triangle_friction_params on a TriangleFault (shared by all
+    members); the constants as in friction_params."""
     rng = np.random.default_rng(seed)
     n = f.n
     amb = rng.uniform(-0.006, 0.004, (n, members))
     dc = 10.0 ** rng.uniform(np.log10(0.005), np.log10(0.05), (n, members))
     b = np.full((n, members), 0.015)
-    return dict(a=b + amb, b=b, dc=dc, sigma=np.full(n, 50.0e6),
+    sigma = triangle_friction_params(f)["sigma"] if isinstance(f, TriangleFault) else np.full(n, 50.0e6)
+    return dict(a=b + amb, b=b, dc=dc, sigma=sigma,
                 V0=V0, f0=F0, V_pl=V_PL, eta_rad=MU / (2.0 * CS), mu=MU, nu=NU)
 
 
