@@ -139,3 +139,52 @@ def test_graph_batches_and_direct_agree_bitwise(case):
     assert np.array_equal(y1, y2) and np.array_equal(D1, D2)
     assert np.array_equal(e1.t, e2.t) and np.array_equal(e1.rejected, e2.rejected)
     assert np.all(e1.accepted == 10)
+
+
+def test_triangle_fault_with_normal_stress_one_step():
+    """Curved thrust of 384 triangles with its own shear (A) and normal-stress
+    (B) matrices, sigma rising with depth: one step of four members (BF16x6
+    ensemble products with A and with B per stage) against the oracle on the
+    dense FP64 matrices."""
+    import torch
+
+    import paper_2110_12165_amd as hm
+    from oracle.triangles import TriangleGeometry
+    from synth import config_triangle_fault
+    f = config_triangle_fault("thrust_16x12")
+    n, m = f.n, 4
+    A, B = TriangleGeometry(f.verts, f.slip_dir, MU, NU).blocks(np.arange(n), np.arange(n))
+    p = ensemble_params(f, m, 3)
+    V = loguniform_rates(n, 5, nrhs=m)
+    kick = np.random.default_rng(105).uniform(-0.05, 0.05, (n, m))
+    y0 = np.empty((3, n, m))
+    members = []
+    for r in range(m):
+        pr = dict(p, a=p["a"][:, r], b=p["b"][:, r], dc=p["dc"][:, r])
+        yr = fr.initial_state(V[:, r], pr, p["sigma"])
+        yr[:n] += kick[:, r]
+        y0[:, :, r] = yr.reshape(3, n)
+        members.append(pr)
+    # the oracle's dense matrices as single dense blocks, FP32 storage
+    perm = np.arange(n, dtype=np.int32)
+    desc = np.array([[0, 0, n, 0, n, 0]], dtype=np.int64)
+    HA, HB = (hm.HMatrix.from_blocks(n, perm, desc, np.array([0]), M.T.reshape(-1).copy(), prec="f32",
+                                     kernel="split", max_nrhs=64) for M in (A, B))
+    ens, y, D = _gpu(torch, hm, HA, p, y0, 1, "x6", B=HB, dt0=100.0)
+    HA.close()
+    HB.close()
+    say(f"[ensemble rk45] thrust_16x12 N={n}, {m} members, A and B, one step: sigma moved by up to "
+        f"{np.max(np.abs(y[2] - y0[2])):.3e} Pa")
+    for r in range(m):
+        pr = members[r]
+        Vf = lambda yy: fr.slip_rate(yy[:n], yy[n:2 * n], yy[2 * n:], pr["a"], pr["V0"])
+        with np.errstate(over="ignore", invalid="ignore"):   # rejected trial steps may overflow eq. (7)
+            ref = rk45.integrate(lambda yy: fr.rhs(yy, pr, lambda v: A @ v, lambda v: B @ v),
+                                 y0[:, :, r].reshape(-1), 100.0, 1, slip_rate=Vf)
+        assert ens.accepted[r] == 1 and ens.rejected[r] == sum(1 for e in ref["log"] if not e[3])
+        assert ens.t[r] == pytest.approx(ref["t"], rel=1e-15)
+        dy, dref = (y[:, :, r] - y0[:, :, r]), (ref["y"].reshape(3, n) - y0[:, :, r])
+        for c in range(3):
+            assert np.max(np.abs(dref[c])) > 0.0
+            assert np.max(np.abs(dy[c] - dref[c])) <= 2e-5 * np.max(np.abs(dref[c])), (r, c)
+        assert np.max(np.abs(D[:, r] - ref["D"])) <= 2e-5 * np.max(np.abs(ref["D"]))
