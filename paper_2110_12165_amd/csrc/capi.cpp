@@ -133,6 +133,19 @@ struct hmat_s {
   double* rs_ax = nullptr;  // n doubles: A (V - V_pl)
   double* rs_bx = nullptr;  // n doubles: B (V - V_pl)
   hmat_stats st{};
+  // side stream and fork/join events: this handle's product runs beside
+  // another handle's in the same stage (with_pair)
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+
+  // Creates them on the first call (never during a graph capture: the
+  // entry points call this before they capture).
+  void ensure_side() {
+    if (side) return;
+    check_hip(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming), "hipEventCreateWithFlags");
+    check_hip(hipEventCreateWithFlags(&ev_join, hipEventDisableTiming), "hipEventCreateWithFlags");
+    check_hip(hipStreamCreateWithFlags(&side, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+  }
   // captured Runge-Kutta attempts (rs_rk45_run, rs_ens_rk45_run), each keyed
   // by everything it reads
   GraphCache rk_cache, ens_cache;
@@ -146,6 +159,9 @@ struct hmat_s {
     if (!on_device) return;
     (void)hipDeviceSynchronize();
     drop_graph();
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
+    if (ev_join) (void)hipEventDestroy(ev_join);
+    if (side) (void)hipStreamDestroy(side);
     for (void* p : batched_allocs) (void)hipFree(p);
     for (void* p : allocs) (void)hipFree(p);
   }
@@ -913,6 +929,33 @@ void check_rk_args(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D,
   if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
 }
 
+// The products with A and with B of one stage: fa(s), and fb on B's side
+// stream, forked from s and joined back before anything later on s.  On
+// small matrices each product is a few short launches whose ramp and tail
+// leave most of the GPU idle, and the two overlap (under graph capture the
+// fork and the join become dependencies of the graph).  Each handle has
+// its own scratch, so the two are independent and their results do not
+// depend on the overlap; A == B (shared scratch) runs both on s.
+extern "C++" template <class FA, class FB>
+void with_pair(hmat_t A, hmat_t B, hipStream_t s, FA&& fa, FB&& fb) {
+  if (!B) {
+    fa(s);
+    return;
+  }
+  if (B == A) {
+    fa(s);
+    fb(s);
+    return;
+  }
+  B->ensure_side();
+  check_hip(hipEventRecord(B->ev_fork, s), "hipEventRecord");
+  check_hip(hipStreamWaitEvent(B->side, B->ev_fork, 0), "hipStreamWaitEvent");
+  fb(B->side);
+  check_hip(hipEventRecord(B->ev_join, B->side), "hipEventRecord");
+  fa(s);
+  check_hip(hipStreamWaitEvent(s, B->ev_join, 0), "hipStreamWaitEvent");
+}
+
 // Enqueue one attempt: every kernel reads the step from the device state.
 void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const RkWs& w, double* dt_log,
                      hipStream_t s) {
@@ -927,8 +970,9 @@ void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* 
     } else {
       check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, y, w.xv, w.Vs, s), "slip-rate launch");
     }
-    check_hip(A->product(false, w.xv, w.ax, 1.0, 0.0, s, A->kernel), "product launch");
-    if (B) check_hip(B->product(false, w.xv, w.bx, 1.0, 0.0, s, B->kernel), "product launch");
+    with_pair(
+        A, B, s, [&](hipStream_t q) { check_hip(A->product(false, w.xv, w.ax, 1.0, 0.0, q, A->kernel), "product launch"); },
+        [&](hipStream_t q) { check_hip(B->product(false, w.xv, w.bx, 1.0, 0.0, q, B->kernel), "product launch"); });
     check_hip(hm::launch_rs_rhs(n, *p, yin, w.ax, B ? w.bx : nullptr, w.k + stage * n3, s), "rhs launch");
   }
   check_hip(hm::launch_rk_finish_control(n3, w.st, y, w.k, w.y5, s), "error launch");
@@ -989,6 +1033,7 @@ hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, doubl
     const long long target = st->accepted + n_accept;
     put_state(w, st, target, -1, s);
     const bool graph = use_graph && s != nullptr;
+    if (B && B != A) B->ensure_side();  // not during the capture
     if (graph) {
       std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, workspace, dt_log, s};
       for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
@@ -1053,8 +1098,9 @@ void enqueue_frozen_step(hmat_t A, hmat_t B, const rs_params* p, const double* y
     } else {
       check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, y_in, x, nullptr, s), "slip-rate launch");
     }
-    check_hip(A->product(false, x, ax, 1.0, 0.0, s, A->kernel), "product launch");
-    if (B) check_hip(B->product(false, x, bx, 1.0, 0.0, s, B->kernel), "product launch");
+    with_pair(
+        A, B, s, [&](hipStream_t q) { check_hip(A->product(false, x, ax, 1.0, 0.0, q, A->kernel), "product launch"); },
+        [&](hipStream_t q) { check_hip(B->product(false, x, bx, 1.0, 0.0, q, B->kernel), "product launch"); });
     check_hip(hm::launch_rs_rhs(n, *p, yin, ax, B ? bx : nullptr, K + stage * n3, s), "rhs launch");
   }
   check_hip(hm::launch_rk_update_dt(n, dt, p->V0, p->a, K, y_in, y_out, D, s), "update launch");
@@ -1142,8 +1188,10 @@ hmat_status rs_rk45_adjoint(hmat_t A, hmat_t B, const rs_params* p, const double
           const double* Kr = Ks + (l * 6 + r) * n3;
           check_hip(hm::launch_adj_vjp_pre(n, r, dt, *p, Yr, y_bar, Ybar, kbar, gbar, B ? sbar : nullptr, s),
                     "adjoint stage launch");
-          check_hip(A->product(true, gbar, xa, 1.0, 0.0, s, A->kernel), "transpose launch");
-          if (B) check_hip(B->product(true, sbar, xb, 1.0, 0.0, s, B->kernel), "transpose launch");
+          with_pair(
+              A, B, s,
+              [&](hipStream_t q) { check_hip(A->product(true, gbar, xa, 1.0, 0.0, q, A->kernel), "transpose launch"); },
+              [&](hipStream_t q) { check_hip(B->product(true, sbar, xb, 1.0, 0.0, q, B->kernel), "transpose launch"); });
           check_hip(hm::launch_adj_vjp_post(n, *p, Yr, Kr, kbar, xa, B ? xb : nullptr, Ybar + r * n3, a_bar, dc_bar,
                                             s),
                     "adjoint stage launch");
@@ -1198,8 +1246,9 @@ void enqueue_ens_attempt(hmat_t A, hmat_t B, const rs_ens_params* p, double* y, 
     } else {
       check_hip(hm::launch_ens_slip(n, M, p->V0, p->V_pl, p->a, y, w.x, w.Vs, s), "ensemble slip-rate launch");
     }
-    enqueue_mm(A, w.x, M, w.ax, M, M, 1.0, 0.0, p->mode, s);
-    if (B) enqueue_mm(B, w.x, M, w.bx, M, M, 1.0, 0.0, p->mode, s);
+    with_pair(
+        A, B, s, [&](hipStream_t q) { enqueue_mm(A, w.x, M, w.ax, M, M, 1.0, 0.0, p->mode, q); },
+        [&](hipStream_t q) { enqueue_mm(B, w.x, M, w.bx, M, M, 1.0, 0.0, p->mode, q); });
     check_hip(hm::launch_ens_rhs(n, M, p->V0, p->f0, p->eta_rad, p->a, p->b, p->dc, yin, w.ax, B ? w.bx : nullptr,
                                  w.k + stage * n3 * M, s),
               "ensemble rhs launch");
@@ -1248,6 +1297,7 @@ hmat_status rs_ens_rk45_run(hmat_t A, hmat_t B, const rs_ens_params* p, double* 
     check_hip(hipMemcpyAsync(w.st, &d, sizeof(d), hipMemcpyHostToDevice, s), "hipMemcpyAsync");
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
     const bool graph = use_graph && s != nullptr;
+    if (B && B != A) B->ensure_side();  // not during the capture
     if (graph) {
       std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, workspace, s};
       for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
