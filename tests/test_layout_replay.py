@@ -34,3 +34,29 @@ def test_replay(binary, args):
     r = subprocess.run([binary, *args], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True, timeout=600)
     assert r.returncode == 0, r.stdout
     assert r.stdout.strip().endswith("OK")
+
+
+@pytest.fixture(scope="module")
+def binary_sanitized(tmp_path_factory):
+    """The same replay built with AddressSanitizer and UndefinedBehaviorSanitizer
+    (host code only: tree, partition, ACA, packing)."""
+    out = str(tmp_path_factory.mktemp("replay_asan") / "layout_check")
+    srcs = [os.path.join(ROOT, "tests", "cpp", "layout_check.cpp")] + [
+        os.path.join(CSRC, f) for f in HOST_SOURCES]
+    cmd = ["g++", "-O1", "-g", "-std=c++17", "-pthread", "-ffp-contract=off", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer", "-I", os.path.join(ROOT, "include"),
+           "-I", CSRC] + srcs + ["-o", out]
+    subprocess.run(cmd, check=True)
+    return out
+
+
+@pytest.mark.parametrize("args", [
+    ("48", "24", "100", "30", "1", "16", "4", "1e-6"),
+    ("37", "23", "100", "90", "0", "20", "2", "1e-5"),
+    ("3", "2", "100", "90", "0", "1", "1", "1e-6"),
+])
+def test_replay_sanitized(binary_sanitized, args):
+    r = subprocess.run([binary_sanitized, *args], stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True,
+                       timeout=600)
+    assert r.returncode == 0, r.stdout
+    assert r.stdout.strip().endswith("OK")
