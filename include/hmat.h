@@ -329,6 +329,17 @@ typedef struct {
   int64_t rejected;        /* rejected attempts so far */
 } rs_rk45_state;
 
+/* Streams of the integration calls (rs_rk45_attempt, _run, _step, _replay,
+ * _adjoint, rs_ens_rk45_run).  With a B handle other than A, the products
+ * with A and with B of each stage run side by side: A's on `stream`, B's on
+ * a stream that B owns (created at B's first such call unless `stream` is
+ * being captured then, in which case both go on `stream`), forked from
+ * `stream` and joined back before the right-hand side.  Every call stays
+ * ordered on `stream`; the results do not depend on the overlap.  Under the
+ * graph capture of rs_rk45_run / rs_ens_rk45_run the two become parallel
+ * branches of the graph (a handle is used by one stream at a time, as
+ * everywhere: B's own stream is no exception). */
+
 /* Bytes of device workspace rs_rk45_attempt needs for n elements:
  * 8 * (28 n + 32).  n < 0 returns -1. */
 int64_t rs_rk45_workspace_bytes(int64_t n);

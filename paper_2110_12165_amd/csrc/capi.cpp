@@ -947,7 +947,18 @@ void with_pair(hmat_t A, hmat_t B, hipStream_t s, FA&& fa, FB&& fb) {
     fb(s);
     return;
   }
-  B->ensure_side();
+  if (!B->side) {
+    // first pair of this handle: no stream is created while the caller
+    // captures s into a graph of its own (both products then go on s)
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;  // the null stream is never captured
+    if (s) check_hip(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+    if (cs != hipStreamCaptureStatusNone) {
+      fa(s);
+      fb(s);
+      return;
+    }
+    B->ensure_side();
+  }
   check_hip(hipEventRecord(B->ev_fork, s), "hipEventRecord");
   check_hip(hipStreamWaitEvent(B->side, B->ev_fork, 0), "hipStreamWaitEvent");
   fb(B->side);
