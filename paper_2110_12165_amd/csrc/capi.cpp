@@ -453,6 +453,27 @@ void tune_mm(hmat_s* h, hipStream_t s) {
   }
 }
 
+// The persistent schedule's wait for phase 1 is bounded: a workgroup that
+// gives up (about 0.4 s of polling against a phase of ~0.1 ms; never seen)
+// skips phase 2 and counts itself in the error counter, so that launch's
+// results are invalid.  Calls that synchronise anyway (profile, autotune,
+// the Runge-Kutta attempt, step and run) read the counter of the handles
+// they used and fail instead of returning such results.
+void check_wait_flag(hmat_t h, hipStream_t s) {
+  if (!h || !h->on_device || h->kernel != HMAT_KERNEL_BATCHED_PERSISTENT) return;
+  for (hm::QueueCounters* q : {h->batched.ctr, h->has_batched_t ? h->batched_t.ctr : nullptr}) {
+    if (!q) continue;
+    uint32_t e = 0;
+    check_hip(hipMemcpyAsync(&e, &q->error.v, sizeof(e), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    if (e) {
+      check_hip(hipMemsetAsync(&q->error.v, 0, sizeof(e), s), "hipMemsetAsync");
+      hm::fail(HMAT_EDEVICE, "a persistent product gave up waiting for its phase 1; results since the last "
+                             "check are invalid");
+    }
+  }
+}
+
 void fill_stats(hmat_s* h);
 
 hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool on_device = true) {
@@ -862,6 +883,7 @@ hmat_status hmat_profile(hmat_t h, const double* x, double* y, int32_t reps, voi
     out->ms_product = tot / reps;
     out->alg_bytes[0] = nl == 2 ? p1 : st.alg_bytes;
     out->alg_bytes[1] = nl == 2 ? p2 : 0;
+    check_wait_flag(h, s);
   });
 }
 
@@ -1028,6 +1050,8 @@ hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, d
     put_state(w, st, st->accepted + 1, force, s);
     enqueue_attempt(A, B, p, y, D, w, nullptr, s);
     get_state(w, st, s);
+    check_wait_flag(A, s);
+    if (B != A) check_wait_flag(B, s);
   });
 }
 
@@ -1063,6 +1087,8 @@ hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, doubl
       get_state(w, st, s);
       if (st->accepted >= target) break;
     }
+    check_wait_flag(A, s);
+    if (B != A) check_wait_flag(B, s);
     if (st->accepted < target) hm::fail(HMAT_ESTATE, "target not reached within max_attempts");
   });
 }

@@ -215,3 +215,32 @@ def test_rk45_200_steps_free_running(case):
         f"step drift vs free run {drift:.1e}")
     assert rk.state.rejected == sum(1 for e in free["log"] if not e[3])
     assert drift <= 1e-3
+
+
+def test_rk45_with_persistent_products(case):
+    """The attempts and the controlled run with the persistent schedule (one
+    launch per product, bounded phase-1 wait whose flag the synchronising
+    calls read) against the split schedule on the same blocks: states
+    within rounding after 20 steps, same controller decisions."""
+    torch, hm, f, H, p, Hg, dp, dev = case
+    Bk = oracle_blocks(H)
+    Hp = hm.HMatrix.from_blocks(Bk["n"], Bk["perm"], Bk["desc"], Bk["off"], Bk["values"], prec="f64",
+                                kernel="persistent", wg_waves=8, wg_waves_p1=8)
+    assert Hp.info()["kernel"] == "persistent"
+    y0 = _state(f, p, 2, kick=0.05)
+    res = []
+    for H_ in (Hg, Hp):
+        rk = hm.RK45(H_, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+        y = torch.tensor(y0, device=dev)
+        D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+        rk.attempt(y, D)
+        rk.run(y, D, 19, use_graph=False)
+        res.append((y.cpu().numpy(), D.cpu().numpy(), rk.state.accepted, rk.state.rejected, rk.t))
+    Hp.close()
+    (y1, D1, a1, r1, t1), (y2, D2, a2, r2, t2) = res
+    assert (a1, r1) == (a2, r2) and t2 == pytest.approx(t1, rel=1e-12)
+    n = f.n
+    for c in range(3):
+        sl = slice(c * n, (c + 1) * n)
+        assert np.max(np.abs(y2[sl] - y1[sl])) <= 1e-10 * np.max(np.abs(y1[sl]))
+    assert np.max(np.abs(D2 - D1)) <= 1e-10 * np.max(np.abs(D1))
