@@ -62,7 +62,11 @@ typedef enum { HMAT_F64 = 0, HMAT_F32 = 1 } hmat_prec;
  *                        layout (column-major dense blocks and factors).
  *   HMAT_KERNEL_BATCHED: blocks repacked into lane-coalesced panels and
  *                        processed as one list of work units: two launches
- *                        (SPLIT) or one persistent launch (PERSISTENT).
+ *                        (SPLIT) or one persistent launch (PERSISTENT).  The
+ *                        persistent launch's wait for phase 1 is bounded; a
+ *                        launch that gives up (never observed) is reported
+ *                        as HMAT_EDEVICE by the next hmat_profile or
+ *                        rs_rk45_attempt / _step / _run on the handle.
  *   HMAT_KERNEL_AUTO:    BATCHED with the schedule picked by hmat_autotune. */
 typedef enum {
   HMAT_KERNEL_PLAIN = 0,
