@@ -9,6 +9,13 @@ both low-rank phases, row-owned accumulation, scatter back).
 
 The headline value is the FP32-stored / FP64-accumulated batched product;
 the plain FP64 product and the batched FP64 product are timed beside it.
+Further sections of the same JSON line (each can be skipped by a flag):
+construction (host and device), autotuner, size and lattice sweeps, a
+1000-step RK45 run at N = 122880, the 64-member MFMA ensemble product
+(curved thrust of 21000 triangles and the N = 122880 fault), the nonplanar
+fault (A and B products, RK45 with sigma evolving), the 64-member ensemble
+integration and the adjoint gradient on the curved thrust (A and B), and
+the oracle's CPU rate on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
