@@ -797,25 +797,34 @@ def main():
     if "batched_f64" in outputs:
         ref = outputs["batched_f64"]
         line["rel_diff_f32_vs_f64_gpu"] = float(np.linalg.norm(outputs["batched_f32"] - ref) / np.linalg.norm(ref))
+    def section(key, fn, *fargs):
+        # one further section; a failure is logged and recorded under its key,
+        # and the line (headline measured above) is still printed
+        try:
+            line[key] = fn(*fargs)
+        except Exception as e:  # noqa: BLE001
+            log(f"[bench] {key} failed: {type(e).__name__}: {e}")
+            line[key] = {"error": f"{type(e).__name__}: {e}"}
+
     if not args.no_construction:
-        line["construction"] = construction(torch, hm, f, bench_options(WORKLOAD, "batched_f32"), x)
+        section("construction", construction, torch, hm, f, bench_options(WORKLOAD, "batched_f32"), x)
     if not args.no_autotune:
-        line["autotune"] = autotune(torch, hm, f, w, x, args.steps, args.warmup)
+        section("autotune", autotune, torch, hm, f, w, x, args.steps, args.warmup)
     if not args.no_sweeps:
-        line["sweeps"] = sweeps(torch, hm)
+        section("sweeps", sweeps, torch, hm)
     if args.rk_steps > 0:
-        line["rk45"] = rk45_run(torch, hm, f, w, x_np, args.rk_steps)
+        section("rk45", rk45_run, torch, hm, f, w, x_np, args.rk_steps)
     if args.ensemble:
-        line["ensemble"] = ensemble(torch, hm, args.ensemble.split(","))
+        section("ensemble", ensemble, torch, hm, args.ensemble.split(","))
     if not args.no_nonplanar:
-        line["nonplanar"] = nonplanar(torch, hm)
+        section("nonplanar", nonplanar, torch, hm)
     if args.ens_rk_steps > 0:
-        line["ensemble_rk45"] = ensemble_rk(torch, hm, args.ens_rk_steps)
+        section("ensemble_rk45", ensemble_rk, torch, hm, args.ens_rk_steps)
     if args.adjoint_steps > 0:
-        line["adjoint"] = adjoint_run(torch, hm, args.adjoint_steps)
+        section("adjoint", adjoint_run, torch, hm, args.adjoint_steps)
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle sample) ...")
-        line["cpu_baseline"] = cpu_baseline(f, w, x_np, outputs["batched_f32"])
+        section("cpu_baseline", cpu_baseline, f, w, x_np, outputs["batched_f32"])
     print(json.dumps(line), flush=True)
 
 
