@@ -119,3 +119,28 @@ def test_ensemble_degenerate_sizes(groups):
     Hb.matmat(torch.ones((f.n, 5), dtype=torch.float64, device=dev), Y=Y, alpha=1.0, beta=2.0, mode="x6")
     assert torch.equal(Y, 2.0 * Y0)
     Hb.close()
+
+
+def test_autotune_keeps_the_ensemble_product():
+    """hmat_autotune on a handle with ensemble buffers re-lays it out and
+    re-times the wave groups; the ensemble product still agrees with the
+    single-vector products on the new layout."""
+    import torch
+
+    import paper_2110_12165_amd as hm
+    name = "dip30_150x70"
+    w = WORKLOADS[name]
+    f = config_fault(name)
+    Hg = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
+                          lattice=w["lattice"], prec="f32", kernel="split", max_nrhs=64)
+    info = Hg.autotune(reps=3)
+    say(f"[ensemble] autotune picked {info['kernel']} {info['wg_waves']}/{info['wg_waves_p1']}, "
+        f"wave groups {info['mm_groups']}")
+    assert info["kernel"] in ("split", "persistent")
+    assert all(v in (1, 2) for m in info["mm_groups"].values() for v in m)
+    dev = torch.device("cuda:0")
+    X = torch.tensor(loguniform_rates(f.n, 6, nrhs=16), device=dev)
+    Ym = Hg.matmat(X, mode="x6").cpu().numpy()
+    Yv = np.stack([Hg.matvec(X[:, c].contiguous()).cpu().numpy() for c in range(16)], axis=1)
+    Hg.close()
+    assert rel(Ym, Yv) <= 2e-5
