@@ -191,3 +191,37 @@ def test_overlapped_a_and_b_products_are_reproducible():
     assert np.array_equal(y.cpu().numpy(), runs[0][0]) and np.array_equal(D.cpu().numpy(), runs[0][1])
     HA.close()
     HB.close()
+
+
+@pytest.mark.parametrize("component", [0, 1])
+def test_paper_scale_ensemble_product(component):
+    """The 64-member ensemble product on the 21000-triangle fault (A and B),
+    both wave-group settings, against the FP64 plain product of the same
+    mesh and exact rows from the entries."""
+    import torch
+
+    import paper_2110_12165_amd as hm
+    name = "thrust_150x70"
+    w = TRIANGLE_WORKLOADS[name]
+    f = config_triangle_fault(name)
+    dev = torch.device("cuda:0")
+    X = loguniform_rates(f.n, 7, nrhs=6)
+    H64 = _build(hm, f, w, component, "f64", "plain")
+    ref = np.stack([H64.matvec(torch.tensor(np.ascontiguousarray(X[:, c]), device=dev)).cpu().numpy()
+                    for c in range(X.shape[1])], axis=1)
+    H64.close()
+    rows = np.random.default_rng(2).choice(f.n, 4, replace=False)
+    exact = np.array([hm.kernel_entries(f.verts, f.slip_dir, MU, NU, np.full(f.n, i), np.arange(f.n), component)
+                      for i in rows]) @ X
+    assert np.max(np.abs(ref[rows] - exact)) <= 1e-5 * np.max(np.abs(ref))
+    Xd = torch.tensor(X, device=dev)
+    for groups in (1, 2):
+        H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=component, aca_eps=w["aca_eps"], eta=w["eta"],
+                             leaf=w["leaf"], lattice=w["lattice"], prec="f32", kernel="split", build_device=1,
+                             max_nrhs=64, mm_groups=groups)
+        y6 = H.matmat(Xd, mode="x6").cpu().numpy()
+        y3 = H.matmat(Xd, mode="x3").cpu().numpy()
+        H.close()
+        say(f"[triangles] {name} {'AB'[component]} ensemble, groups {groups}: rel x6 {rel(y6, ref):.2e}, "
+            f"x3 {rel(y3, ref):.2e}")
+        assert rel(y6, ref) <= 2e-5 and rel(y3, ref) <= 1e-3
