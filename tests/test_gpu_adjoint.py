@@ -174,11 +174,11 @@ def test_autograd_function(small):
     assert _close(dc.grad.cpu().numpy() - gdc_c.cpu().numpy(), gdc_r) <= tol
 
 
-def _target_at(hm, Hg, p, a, b, dc, y0, T):
+def _target_at(hm, Hg, p, a, b, dc, y0, T, HB=None):
     """Slip at time T of the controlled integration with parameters (a, b,
     dc): steps while they end before T, then one forced step to T."""
     import torch
-    rk = hm.RK45(Hg, None, a, b, dc, p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    rk = hm.RK45(Hg, HB, a, b, dc, p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
     y = torch.tensor(y0, device=a.device)
     D = torch.zeros(len(y0) // 3, dtype=torch.float64, device=a.device)
     while rk.t + rk.dt < T:
@@ -266,6 +266,83 @@ def test_adjoint_against_central_differences_paper_scale(paper_scale):
             fd = (loss(*args_p) - loss(*args_m)) / (2 * h)
             err = abs(fd - g[i]) / (abs(g[i]) + 1e-2 * scale)
             worst = max(worst, err)
+            say(f"   {key}[{int(i)}]: adjoint {g[i]: .6e}  central difference {fd: .6e}")
+            assert abs(fd - g[i]) <= 1e-4 * abs(g[i]) + 1e-6 * scale, (key, int(i), fd, g[i])
+    say(f"   worst FD mismatch (relative): {worst:.2e}")
+
+
+@pytest.fixture(scope="module")
+def paper_scale_triangles():
+    """The curved thrust of 21000 triangles with its shear (A) and normal (B)
+    matrices, FP32 factors built on the device, sigma rising with depth; the
+    first WINDOW steps of the controlled run from a kicked steady state."""
+    import torch
+
+    import paper_2110_12165_amd as hm
+    from synth import TRIANGLE_WORKLOADS, config_triangle_fault, triangle_friction_params
+    name = "thrust_150x70"
+    w = TRIANGLE_WORKLOADS[name]
+    f = config_triangle_fault(name)
+    p = triangle_friction_params(f)
+    dev = torch.device("cuda:0")
+    HA, HB = (hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=c, aca_eps=w["aca_eps"], eta=w["eta"],
+                               leaf=w["leaf"], lattice=w["lattice"], prec="f32", kernel="split", build_device=1)
+              for c in (0, 1))
+    dp = {k: torch.tensor(p[k], device=dev) for k in ("a", "b", "dc")}
+    y0 = _state(f, p, 3)
+    rk = hm.RK45(HA, HB, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    log = torch.zeros(WINDOW, dtype=torch.float64, device=dev)
+    rk.run(y, D, WINDOW, use_graph=False, dt_log=log)
+    dts = log.cpu().numpy()
+    n = f.n
+    yn = y.cpu().numpy()
+    vmax = float(np.max(fr.slip_rate(yn[:n], yn[n:2 * n], yn[2 * n:], p["a"], p["V0"])))
+    at = dp["a"] + torch.tensor(np.random.default_rng(4).uniform(-1e-3, 1e-3, n), device=dev)
+    D_t, steps_t = _target_at(hm, HA, p, at, dp["b"], dp["dc"], y0, rk.t, HB=HB)
+    say(f"[paper scale, triangles] N={n}, A and B, {WINDOW} steps to t={rk.t:.4e} s, largest slip "
+        f"{float(D.max()):.3e} m, largest slip rate {vmax:.2e} m/s, sigma moved by up to "
+        f"{np.max(np.abs(yn[2 * n:] - y0[2 * n:])):.3e} Pa; target: {steps_t} steps")
+    assert np.isfinite(vmax) and torch.isfinite(D_t).all()
+    yield torch, hm, f, p, HA, HB, dp, y0, dts, D_t
+    HA.close()
+    HB.close()
+
+
+def test_adjoint_against_central_differences_triangles(paper_scale_triangles):
+    """As the planar paper-scale check, with the normal stress evolving
+    through B (its transpose enters the adjoint): 10 elements."""
+    torch, hm, f, p, HA, HB, dp, y0, dts, D_t = paper_scale_triangles
+    dev = dp["a"].device
+    rk = hm.RK45(HA, HB, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+    y = torch.tensor(y0, device=dev)
+    D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+    ckpt = rk.replay(y, D, dts, ckpt_every=50)
+    Dbar = D - D_t
+    _, ga, gdc = rk.adjoint(ckpt, dts, 50, torch.zeros_like(y), Dbar)
+    ga, gdc = ga.cpu().numpy(), gdc.cpu().numpy()
+
+    def loss(a, dc):
+        r = hm.RK45(HA, HB, a, dp["b"], dc, p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+        yy = torch.tensor(y0, device=dev)
+        DD = torch.zeros(f.n, dtype=torch.float64, device=dev)
+        r.replay(yy, DD, dts)
+        return 0.5 * float(((DD - D_t) ** 2).sum())
+
+    h = 1e-6
+    idx = np.random.default_rng(5).choice(f.n, 10, replace=False)
+    worst = 0.0
+    for key, g in (("a", ga), ("dc", gdc)):
+        scale = np.max(np.abs(g))
+        for i in idx:
+            tp, tm = dp[key].clone(), dp[key].clone()
+            tp[i] += h
+            tm[i] -= h
+            args_p = (tp, dp["dc"]) if key == "a" else (dp["a"], tp)
+            args_m = (tm, dp["dc"]) if key == "a" else (dp["a"], tm)
+            fd = (loss(*args_p) - loss(*args_m)) / (2 * h)
+            worst = max(worst, abs(fd - g[i]) / (abs(g[i]) + 1e-2 * scale))
             say(f"   {key}[{int(i)}]: adjoint {g[i]: .6e}  central difference {fd: .6e}")
             assert abs(fd - g[i]) <= 1e-4 * abs(g[i]) + 1e-6 * scale, (key, int(i), fd, g[i])
     say(f"   worst FD mismatch (relative): {worst:.2e}")
