@@ -12,7 +12,7 @@ Three forms of the same definition:
   (up to rounding) with zero-padded FFTs.  The grid is indexed
   k = iy * nx + ix as in ``synth``.
 
-Pins (tests/test_oracle_dense.py): the FFT form against the explicit
+Pins (tests/test_oracle_hmatrix.py): the FFT form against the explicit
 matrix, the row form against the explicit matrix.
 """
 from __future__ import annotations

@@ -21,7 +21,11 @@ Pins (tests/test_oracle_friction.py): round trip V(tau(V)) = V; the partial
 derivatives against complex-step derivatives; the steady-state friction
 against f0 + (a-b) ln(V/V0); the plate-rate fixed point dy/dt = 0; the
 radiation-damping elimination of eq. (11) checked by finite differences of
-a quasi-dynamic force balance.
+a quasi-dynamic force balance; the state rate of eq. (8) away from steady
+state against the theta form of the aging law (dtheta/dt = 1 - V theta/d_c);
+the critical stiffness of a one-element spring-slider, where the linearised
+right-hand side loses stability, against sigma (b - a) / d_c (less the
+radiation-damping shift eta V_pl / d_c).
 """
 from __future__ import annotations
 

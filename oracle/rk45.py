@@ -22,7 +22,10 @@ A non-finite error counts as a rejection with dt / 2.
 Pins (tests/test_oracle_rk45.py): the tableau satisfies the order
 conditions of a 5th-order (b5) and 4th-order (b4) method in exact rational
 arithmetic; the observed convergence orders on y' = -y are 5 and 4; the
-controller follows eqs. (14)-(15) on scripted errors.
+controller follows eqs. (14)-(15) on scripted errors; the slip of eq. (16)
+is exact for a slip rate linear in time and over-integrates a quadratic one
+by exactly dt^3/6 per step (the trapezoidal rule's error), and rejected
+attempts leave it unchanged.
 """
 from __future__ import annotations
 

@@ -76,3 +76,64 @@ def test_radiation_damping_balance():
     dVdt = (Vof(y + h * dydt) - Vof(y - h * dydt)) / (2 * h)
     lhs = dydt[n:2 * n] + p["eta_rad"] * dVdt
     np.testing.assert_allclose(lhs, A @ (V - p["V_pl"]), rtol=1e-6, atol=1e-6 * np.max(np.abs(A @ V)))
+
+
+def test_state_rate_matches_the_theta_form_of_the_aging_law():
+    """Eq. (8) in the state variable theta of the aging law.  With
+    theta = (d_c / V0) exp((phi - f0) / b) the aging law reads
+    dtheta/dt = 1 - V theta / d_c, and phi = f0 + b ln(V0 theta / d_c) gives
+    dphi/dt = (b / theta) dtheta/dt.  Checked away from steady state, so the
+    size of the rate (its b / d_c prefactor) is pinned, not only its zero."""
+    n = 6
+    p = _p(n)
+    rng = np.random.default_rng(7)
+    sig = rng.uniform(20e6, 100e6, n)
+    V = 10.0 ** rng.uniform(-12, -2, n)
+    phi = fr.steady_state_phi(V, p["b"], V0, F0) + rng.uniform(-0.08, 0.08, n)
+    y = np.concatenate([phi, fr.shear_traction(V, phi, sig, p["a"], V0), sig])
+    dydt, Vr = fr.rhs(y, p, lambda x: np.zeros_like(x))
+    theta = p["dc"] / V0 * np.exp((phi - F0) / p["b"])
+    dtheta = 1.0 - Vr * theta / p["dc"]
+    np.testing.assert_allclose(dydt[:n], p["b"] / theta * dtheta, rtol=1e-9)
+    # the state is far from steady state: the rates are not near zero
+    assert np.min(np.abs(dtheta)) > 0.05
+
+
+def _spring_slider_growth(k, sig, a, b, dc, eta):
+    """Largest real part of the eigenvalues of the oracle's right-hand side,
+    linearised (central differences) at the plate-rate steady state of one
+    element loaded through the stiffness matrix A = [[-k]]."""
+    p = dict(a=np.array([a]), b=np.array([b]), dc=np.array([dc]), V0=V0, f0=F0, eta_rad=eta, V_pl=1e-9)
+    y0 = fr.initial_state(p["V_pl"], p, np.array([sig]))
+
+    def f(y):
+        return fr.rhs(y, p, lambda x: -k * x)[0][:2]
+    J = np.zeros((2, 2))
+    for c, h in ((0, 1e-7), (1, 1e-7 * sig * a)):
+        e = np.zeros(3)
+        e[c] = h
+        J[:, c] = (f(y0 + e) - f(y0 - e)) / (2 * h)
+    return np.max(np.linalg.eigvals(J).real)
+
+
+def test_spring_slider_critical_stiffness():
+    """Linear stability of one element under the aging law (eqs. 7, 8, 12):
+    the steady state at the plate rate loses stability (Hopf) where the
+    stiffness falls below k_c = (sigma (b - a) - eta V_pl) / d_c (the
+    Ruina-Rice spring-slider result; eta V_pl is the radiation-damping
+    shift).  The oracle's own right-hand side, linearised numerically, must
+    put the crossing there."""
+    sig, a, b, dc, eta = 50e6, 0.010, 0.015, 0.01, 32e9 / (2 * 3464.0)
+    kc = (sig * (b - a) - eta * 1e-9) / dc
+    assert _spring_slider_growth(0.9 * kc, sig, a, b, dc, eta) > 0
+    assert _spring_slider_growth(1.1 * kc, sig, a, b, dc, eta) < 0
+    lo, hi = 0.9 * kc, 1.1 * kc
+    for _ in range(40):
+        mid = 0.5 * (lo + hi)
+        if _spring_slider_growth(mid, sig, a, b, dc, eta) > 0:
+            lo = mid
+        else:
+            hi = mid
+    assert 0.5 * (lo + hi) == pytest.approx(kc, rel=1e-4)
+    # velocity strengthening (a > b): stable at any stiffness
+    assert _spring_slider_growth(1e3, sig, 0.015, 0.010, dc, eta) < 0

@@ -76,3 +76,41 @@ def test_integrate_decay_and_rejections():
     # first attempt (dt = 1) must be rejected for this stiff-ish rate, then grow
     assert any(not acc for _, _, _, acc in out["log"])
     np.testing.assert_allclose(out["y"], np.array([1.0, 2.0, 3.0]) * np.exp(-lam * out["t"]), rtol=1e-4)
+
+
+def _clock_system(V_of_t):
+    """A 3-component system whose first component is the time itself
+    (dy0/dt = 1), with the slip rate a given function of it."""
+    f = lambda y: (np.array([1.0, 0.0, 0.0]), None)
+    return f, (lambda y: np.array([V_of_t(y[0])]))
+
+
+def test_slip_update_is_the_trapezoidal_rule():
+    """Eq. (16): D += dt/2 (V(t) + V(t + dt)) on each accepted step.
+    With V linear in time the trapezoidal rule is exact, so D(t) =
+    V0 t + c t^2 / 2 after any sequence of steps; with V = t^2 each step
+    over-integrates by exactly dt^3 / 6, which tells the trapezoidal rule
+    apart from other rules that are exact for linear V."""
+    V0, c = 2e-9, 3e-7
+    f, V = _clock_system(lambda t: V0 + c * t)
+    out = rk45.integrate(f, np.zeros(3), 0.37, 12, slip_rate=V)
+    t = out["t"]
+    dts = [dt for _, dt, _, acc in out["log"] if acc]
+    assert len(set(dts)) > 5                      # the steps vary (the controller doubles them)
+    assert out["D"][0] == pytest.approx(V0 * t + 0.5 * c * t * t, rel=1e-13)
+    f, V = _clock_system(lambda t: t * t)
+    out = rk45.integrate(f, np.zeros(3), 0.37, 12, slip_rate=V)
+    dts = np.array([dt for _, dt, _, acc in out["log"] if acc])
+    t = out["t"]
+    assert out["D"][0] == pytest.approx(t ** 3 / 3.0 + np.sum(dts ** 3) / 6.0, rel=1e-12)
+
+
+def test_slip_update_uses_only_accepted_steps():
+    """Rejected attempts leave D alone (eq. 16 is applied on acceptance):
+    forced rejections in a replayed schedule do not change the slip."""
+    f, V = _clock_system(lambda t: 1.0 + t)
+    sched = [(0.5, True), (4.0, False), (0.25, True), (8.0, False), (0.125, True)]
+    out = rk45.integrate(f, np.zeros(3), 1.0, 3, slip_rate=V, dt_schedule=sched)
+    t = 0.875
+    assert out["t"] == t
+    assert out["D"][0] == pytest.approx(t + 0.5 * t * t, rel=1e-15)
