@@ -65,8 +65,9 @@ typedef enum { HMAT_F64 = 0, HMAT_F32 = 1 } hmat_prec;
  *                        (SPLIT) or one persistent launch (PERSISTENT).  The
  *                        persistent launch's wait for phase 1 is bounded; a
  *                        launch that gives up (never observed) is reported
- *                        as HMAT_EDEVICE by the next hmat_profile or
- *                        rs_rk45_attempt / _step / _run on the handle.
+ *                        as HMAT_EDEVICE by the next hmat_check,
+ *                        hmat_profile or rs_rk45_attempt / _step / _run on
+ *                        the handle.
  *   HMAT_KERNEL_AUTO:    BATCHED with the schedule picked by hmat_autotune. */
 typedef enum {
   HMAT_KERNEL_PLAIN = 0,
@@ -298,6 +299,18 @@ typedef struct {
  * stream; creates and destroys its own events.
  */
 hmat_status hmat_profile(hmat_t h, const double* x, double* y, int32_t reps, void* stream, hmat_profile_t* out);
+
+/*
+ * hmat_check — report whether every product on the handle since the last
+ * check produced valid results.  Only the persistent schedule can fail
+ * silently (a workgroup that gave up its bounded wait for phase 1): for a
+ * handle using it, waits for `stream`, reads the device flag, clears it and
+ * returns HMAT_EDEVICE if it was set.  Other handles: HMAT_OK at once,
+ * without waiting.  The asynchronous calls (hmat_matvec, _matvec_T,
+ * rs_rk45_replay, rs_rk45_adjoint) do not check by themselves; call this
+ * after them where their results are used.
+ */
+hmat_status hmat_check(hmat_t h, void* stream);
 
 /* Rate-and-state parameters for rs_rhs (section 2.2; section 4.1 loading). */
 typedef struct {

@@ -208,6 +208,11 @@ class HMatrix:
         return dict(n_launches=nl, reps=pr.reps, ms=[pr.ms[i] for i in range(nl)], ms_product=pr.ms_product,
                     alg_bytes=[pr.alg_bytes[i] for i in range(nl)])
 
+    def check(self, stream=None):
+        """hmat_check: raise HmatError if a persistent product on this handle
+        since the last check gave up (waits for the stream only then)."""
+        check(self._lib.hmat_check(self._h, _stream_ptr(stream)))
+
     def autotune(self, reps=20, stream=None):
         check(self._lib.hmat_autotune(self._h, reps, _stream_ptr(stream)))
         return self.info()
@@ -298,6 +303,11 @@ class RK45:
                               max_attempts, None if dt_log is None else _dptr(dt_log), 1 if use_graph else 0,
                               _stream_ptr(stream)))
 
+    def _check_handles(self, stream):
+        self.A.check(stream)
+        if self.B is not None and self.B is not self.A:
+            self.B.check(stream)
+
     def replay(self, y, D, dts, ckpt_every=0, stream=None):
         """The integration on the frozen steps dts (rs_rk45_replay): y (and D,
         unless None) advance in place.  With ckpt_every > 0 returns the
@@ -312,11 +322,12 @@ class RK45:
         ckpt = None
         if ckpt_every > 0:
             ckpt = torch.empty(((m + ckpt_every - 1) // ckpt_every) * 3 * n, dtype=torch.float64, device=y.device)
-        check(_lib.load().rs_rk45_replay(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
-                                         _dptr(y), None if D is None else _dptr(D),
-                                         d.ctypes.data_as(C.POINTER(C.c_double)), m,
-                                         None if ckpt is None else _dptr(ckpt), max(ckpt_every, 1),
-                                         _dptr(self.workspace), _stream_ptr(stream)))
+        lib = _lib.load()
+        args = (self.A._h, None if self.B is None else self.B._h, C.byref(self.params), _dptr(y),
+                None if D is None else _dptr(D), d.ctypes.data_as(C.POINTER(C.c_double)), m,
+                None if ckpt is None else _dptr(ckpt), max(ckpt_every, 1))
+        check(lib.rs_rk45_replay(*args, _dptr(self.workspace), _stream_ptr(stream)))
+        self._check_handles(stream)
         return ckpt
 
     def adjoint(self, ckpt, dts, ckpt_every, y_bar, D_bar=None, a_bar=None, dc_bar=None, stream=None):
@@ -350,6 +361,7 @@ class RK45:
                                   None if D_bar is None else _dptr(D_bar), _dptr(y_bar), _dptr(a_bar),
                                   _dptr(dc_bar), _dptr(self._adj_ws), self._adj_ws.numel() * 8,
                                   _stream_ptr(stream)))
+        self._check_handles(stream)
         return y_bar, a_bar, dc_bar
 
     @property

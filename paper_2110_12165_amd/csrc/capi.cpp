@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 #include <cmath>
 #include <cstring>
@@ -97,15 +98,28 @@ struct GraphCache {
   }
 };
 
+void push_u64(std::vector<const void*>& key, uint64_t v) {
+  key.push_back(reinterpret_cast<const void*>(static_cast<uintptr_t>(v)));
+}
+
 void push_double(std::vector<const void*>& key, double c) {
   const void* v;
   std::memcpy(&v, &c, sizeof(v));
   key.push_back(v);
 }
 
+// Identity of a handle for the graph caches of other handles: never reused
+// within the process (a new handle may land at a freed handle's address).
+std::atomic<uint64_t> g_next_uid{1};
+
 struct hmat_s {
   int device = 0;
   bool on_device = false;  // false: host blocks only (hmat_build_host)
+  const uint64_t uid = g_next_uid.fetch_add(1);
+  // Bumped whenever the product's buffers or schedule change (drop_batched,
+  // setup_batched, tune_mm, hmat_autotune): a graph captured with this
+  // handle's kernels is valid only for the generation it was captured at.
+  uint64_t gen = 0;
   hm::HostMatrix H;
   hmat_opts opts{};
   int32_t kernel = HMAT_KERNEL_BATCHED_SPLIT;  // resolved
@@ -190,6 +204,7 @@ struct hmat_s {
 
   void drop_batched() {
     (void)hipDeviceSynchronize();
+    ++gen;
     drop_graph();
     for (void* p : batched_allocs) (void)hipFree(p);
     batched_allocs.clear();
@@ -336,6 +351,7 @@ struct hmat_s {
     opts.wg_waves = wg;
     opts.wg_waves_p1 = wg1;
     opts.unit_kib = (int32_t)(unit_bytes / 1024);
+    ++gen;
     check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
   }
 
@@ -416,6 +432,7 @@ constexpr int kMMTuneReps = 5;  // timed ensemble products per mode and wave-gro
 void tune_mm(hmat_s* h, hipStream_t s) {
   if (h->opts.mm_groups) {
     for (auto& m : h->mm_groups) m[0] = m[1] = h->opts.mm_groups;
+    ++h->gen;
     return;
   }
   struct Buf {
@@ -451,6 +468,7 @@ void tune_mm(hmat_s* h, hipStream_t s) {
     }
     for (int p = 0; p < 2; ++p) h->mm_groups[m][p] = ms[1][p] < ms[0][p] ? 2 : 1;
   }
+  ++h->gen;
 }
 
 // The persistent schedule's wait for phase 1 is bounded: a workgroup that
@@ -475,6 +493,18 @@ void check_wait_flag(hmat_t h, hipStream_t s) {
 }
 
 void fill_stats(hmat_s* h);
+
+// The handles a captured attempt runs kernels of: identity, generation and
+// schedule of A and of B (B's buffers are baked into A's graph; a B that
+// was re-laid out or destroyed, even if a new handle took its address,
+// no longer matches and the attempt is captured again).
+void push_handle_key(std::vector<const void*>& key, hmat_t A, hmat_t B) {
+  for (hmat_t h : {A, B}) {
+    push_u64(key, h ? h->uid : 0);
+    push_u64(key, h ? h->gen : 0);
+    push_u64(key, h ? (uint64_t)h->kernel : 0);
+  }
+}
 
 hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool on_device = true) {
   auto h = std::make_unique<hmat_s>();
@@ -833,6 +863,8 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
     h->kernel = best_k;
     if (best_k != HMAT_KERNEL_PLAIN) h->setup_batched_any(best_w, (int64_t)best_u * 1024, best_w1, s);
     if (best_k != HMAT_KERNEL_PLAIN && h->mm_xs) tune_mm(h, s);
+    ++h->gen;
+    h->drop_graph();
     refresh_stats(h);
   });
 }
@@ -1070,8 +1102,9 @@ hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, doubl
     const bool graph = use_graph && s != nullptr;
     if (B && B != A) B->ensure_side();  // not during the capture
     if (graph) {
-      std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, workspace, dt_log, s};
+      std::vector<const void*> key{p->a, p->b, p->dc, y, D, workspace, dt_log, s};
       for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
+      push_handle_key(key, A, B);
       A->rk_cache.ensure(key, s, [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, dt_log, cs); });
     }
     int64_t launched = 0;
@@ -1147,6 +1180,31 @@ bool transposable(hmat_t h) { return h->has_batched_t || (h->has_plain && h->pla
 
 }  // namespace
 
+namespace {
+
+// The frozen-step integration of rs_rk45_replay on a workspace of at least
+// replay_doubles(n) doubles (stage derivatives 18n, stage input 3n, x, A x,
+// B x); every part is written before it is read.
+int64_t replay_doubles(int64_t n) { return 24 * n; }
+
+void enqueue_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const double* dts,
+                    int64_t n_steps, double* ckpt, int64_t ckpt_every, double* ws, hipStream_t s) {
+  const int64_t n = A->H.n, n3 = 3 * n;
+  double* K = ws;  // 18n, then ys 3n, x, ax, bx
+  double* ys = K + 6 * n3;
+  double* x = ys + n3;
+  double* ax = x + n;
+  double* bx = ax + n;
+  for (int64_t m = 0; m < n_steps; ++m) {
+    if (ckpt && m % ckpt_every == 0)
+      check_hip(hipMemcpyAsync(ckpt + (m / ckpt_every) * n3, y, n3 * sizeof(double), hipMemcpyDeviceToDevice, s),
+                "checkpoint copy");
+    enqueue_frozen_step(A, B, p, y, y, D, dts[m], K, nullptr, ys, x, ax, bx, s);
+  }
+}
+
+}  // namespace
+
 hmat_status rs_rk45_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const double* dts,
                            int64_t n_steps, double* ckpt, int64_t ckpt_every, void* workspace, void* stream) {
   return guarded([&] {
@@ -1155,19 +1213,17 @@ hmat_status rs_rk45_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, do
     if (reinterpret_cast<uintptr_t>(workspace) % 8) hm::fail(HMAT_EINVAL, "workspace must be 8-byte aligned");
     if (n_steps == 0) return;
     DeviceGuard g(A->device);
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t n = A->H.n, n3 = 3 * n;
-    double* K = static_cast<double*>(workspace);  // 18n, then ys 3n, x, ax, bx
-    double* ys = K + 6 * n3;
-    double* x = ys + n3;
-    double* ax = x + n;
-    double* bx = ax + n;
-    for (int64_t m = 0; m < n_steps; ++m) {
-      if (ckpt && m % ckpt_every == 0)
-        check_hip(hipMemcpyAsync(ckpt + (m / ckpt_every) * n3, y, n3 * sizeof(double), hipMemcpyDeviceToDevice, s),
-                  "checkpoint copy");
-      enqueue_frozen_step(A, B, p, y, y, D, dts[m], K, nullptr, ys, x, ax, bx, s);
-    }
+    enqueue_replay(A, B, p, y, D, dts, n_steps, ckpt, ckpt_every, static_cast<double*>(workspace),
+                   static_cast<hipStream_t>(stream));
+  });
+}
+
+hmat_status hmat_check(hmat_t h, void* stream) {
+  return guarded([&] {
+    if (!h) hm::fail(HMAT_EINVAL, "null handle");
+    if (!h->on_device) return;
+    DeviceGuard g(h->device);
+    check_wait_flag(h, static_cast<hipStream_t>(stream));
   });
 }
 
@@ -1336,9 +1392,10 @@ hmat_status rs_ens_rk45_run(hmat_t A, hmat_t B, const rs_ens_params* p, double* 
     const bool graph = use_graph && s != nullptr;
     if (B && B != A) B->ensure_side();  // not during the capture
     if (graph) {
-      std::vector<const void*> key{B, p->a, p->b, p->dc, y, D, workspace, s};
+      std::vector<const void*> key{p->a, p->b, p->dc, y, D, workspace, s};
       for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
       key.push_back(reinterpret_cast<const void*>((intptr_t)(M * 16 + p->mode)));
+      push_handle_key(key, A, B);
       A->ens_cache.ensure(key, s, [&](hipStream_t cs) { enqueue_ens_attempt(A, B, p, y, D, w, cs); });
     }
     int64_t launched = 0;
