@@ -11,14 +11,27 @@ Indices: blocks refer to rows/columns in cluster order (positions in the
 tree permutation ``perm``); user-order vectors are gathered with ``perm``
 before the product and scattered back after it.
 
+Two forms of the same product: ``HMatrix.matvec`` loops over the blocks;
+``SparseHMatrix`` holds the same blocks as three sparse matrices, the dense
+blocks D (N x N) and the stacked factors U (N x R) and V (N x R), R the sum
+of the ranks, so that H = D + U V^T and y = D x + U (V^T x) (eq. (20) with
+all blocks at once; row chunks may run on threads, each row's sum is taken
+the same way either way).  ``HMatrix.from_arrays`` reads blocks in the
+layout of the library's export (column-major dense blocks; U then V).
+
 Pins (tests/test_oracle_hmatrix.py): the H product against the plain
 product y = A x (relative error of the order of the ACA tolerance),
 exactly low-rank blocks reproduced, linearity, the transpose identity
-<y, H x> = <H^T y, x>, the symmetric kernel giving H^T x ~ H x.
+<y, H x> = <H^T y, x>, the symmetric kernel giving H^T x ~ H x; the sparse
+form against the block loop (both products), threaded against unthreaded
+(identical bits), and the array layout read back block for block.
 """
 from __future__ import annotations
 
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
+import scipy.sparse as sp
 
 from .aca import aca
 from .cluster import ClusterTree, partition
@@ -78,6 +91,25 @@ class HMatrix:
         h.tree = tree
         h.lattice = lattice
         return h
+
+    @classmethod
+    def from_arrays(cls, n, perm, desc, off, values):
+        """Blocks given as arrays: desc (nb, 6) = kind (0 dense, 1 low rank),
+        r0, m, c0, n, rank; off[b] = first value of block b in values; a
+        dense block is m x n column-major, a low-rank block U (m x rank)
+        then V (n x rank), both column-major."""
+        desc = np.asarray(desc, dtype=np.int64).reshape(-1, 6)
+        values = np.asarray(values, dtype=np.float64)
+        blocks = []
+        for (kind, r0, m, c0, nn, r), o in zip(desc, np.asarray(off, dtype=np.int64)):
+            r0, m, c0, nn, r, o = int(r0), int(m), int(c0), int(nn), int(r), int(o)
+            if kind == 0:
+                blocks.append(Block("dense", r0, m, c0, nn, D=values[o:o + m * nn].reshape(nn, m).T))
+            else:
+                U = values[o:o + m * r].reshape(r, m).T
+                V = values[o + m * r:o + (m + nn) * r].reshape(r, nn).T
+                blocks.append(Block("lr", r0, m, c0, nn, U=U, V=V))
+        return cls(n, perm, blocks)
 
     def lattice_row_ranges(self, rows):
         """[start, end) of the given lattice block-rows in cluster order."""
@@ -139,3 +171,93 @@ class HMatrix:
                     lr_entries=lr_e, entries=dense_e + lr_e,
                     max_rank=max(ranks) if ranks else 0,
                     compression=(dense_e + lr_e) / float(self.n) ** 2)
+
+
+class SparseHMatrix:
+    """The blocks of an HMatrix as H = D + U V^T with sparse D (N x N), U and
+    V (N x R) in cluster order; products in user order like HMatrix's.
+    threads > 1 splits the rows of each sparse product into chunks taken
+    by a thread pool (scipy's sparse products release the interpreter
+    lock); a row's sum does not depend on the split."""
+
+    def __init__(self, H, threads=1):
+        n = H.n
+        self.n = n
+        self.perm = np.asarray(H.perm, dtype=np.int64)
+        self.threads = max(1, int(threads))
+        dr, dc, dv = [], [], []
+        ur, uc, uv = [], [], []
+        vptr, vidx, vv = [np.zeros(1, dtype=np.int64)], [], []
+        R = 0
+        for b in H.blocks:
+            if b.kind == "dense":
+                i, j = np.meshgrid(np.arange(b.r0, b.r0 + b.m, dtype=np.int32),
+                                   np.arange(b.c0, b.c0 + b.n, dtype=np.int32), indexing="ij")
+                dr.append(i.ravel())
+                dc.append(j.ravel())
+                dv.append(np.asarray(b.D, dtype=np.float64).ravel())
+            elif b.rank:
+                i, k = np.meshgrid(np.arange(b.r0, b.r0 + b.m, dtype=np.int32),
+                                   np.arange(R, R + b.rank, dtype=np.int32), indexing="ij")
+                ur.append(i.ravel())
+                uc.append(k.ravel())
+                uv.append(np.asarray(b.U, dtype=np.float64).ravel())
+                # row R + l of V^T is column l of V: columns c0 .. c0 + n of H
+                vptr.append(np.full(b.rank, b.n, dtype=np.int64))
+                vidx.append(np.tile(np.arange(b.c0, b.c0 + b.n, dtype=np.int32), b.rank))
+                vv.append(np.asarray(b.V, dtype=np.float64).T.ravel())
+                R += b.rank
+        self.R = R
+
+        def csr(rows, cols, vals, shape):
+            if not rows:
+                return sp.csr_matrix(shape)
+            return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                                 shape=shape).tocsr()
+        self.D = csr(dr, dc, dv, (n, n))
+        self.U = csr(ur, uc, uv, (n, max(R, 1)))
+        if R:
+            self.Vt = sp.csr_matrix((np.concatenate(vv), np.concatenate(vidx), np.cumsum(np.concatenate(vptr))),
+                                    shape=(R, n))
+        else:
+            self.Vt = sp.csr_matrix((1, n))
+        self._T = None                                      # (D^T, U^T, V), built on first use
+        self._chunks = {}
+        self._pool = ThreadPoolExecutor(self.threads) if self.threads > 1 else None
+
+    @property
+    def nnz(self):
+        return self.D.nnz + self.U.nnz + self.Vt.nnz
+
+    def _mv(self, M, x):
+        if self._pool is None or M.shape[0] < 4 * self.threads:
+            return M @ x
+        key = id(M)
+        if key not in self._chunks:
+            edges = np.linspace(0, M.shape[0], 4 * self.threads + 1).astype(np.int64)
+            self._chunks[key] = [M[a:b] for a, b in zip(edges[:-1], edges[1:]) if b > a]
+        return np.concatenate(list(self._pool.map(lambda c: c @ x, self._chunks[key])))
+
+    def matvec(self, x):
+        x = np.asarray(x, dtype=np.float64)
+        xc = x[self.perm]
+        yc = self._mv(self.D, xc) + self._mv(self.U, self._mv(self.Vt, xc))
+        y = np.empty_like(yc)
+        y[self.perm] = yc
+        return y
+
+    def matvec_T(self, x):
+        if self._T is None:
+            self._T = (self.D.T.tocsr(), self.U.T.tocsr(), self.Vt.T.tocsr())
+        Dt, Ut, V = self._T
+        x = np.asarray(x, dtype=np.float64)
+        xc = x[self.perm]
+        yc = self._mv(Dt, xc) + self._mv(V, self._mv(Ut, xc))
+        y = np.empty_like(yc)
+        y[self.perm] = yc
+        return y
+
+    def close(self):
+        if self._pool is not None:
+            self._pool.shutdown()
+            self._pool = None
