@@ -416,6 +416,23 @@ hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, doub
 hmat_status rs_rk45_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const double* dts,
                            int64_t n_steps, double* ckpt, int64_t ckpt_every, void* workspace, void* stream);
 
+/*
+ * rs_rk45_replay_noalloc — rs_rk45_replay without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc).  Same arguments, results
+ * and stream ordering as rs_rk45_replay; the 24 n doubles of workspace come
+ * from a static device array of 32 MiB in the library (one per device,
+ * held until the process ends), so n is at most
+ * rs_rk45_replay_noalloc_max_n() = 174762 (HMAT_EINVAL beyond).  Calls no
+ * allocating routine.  Every call on a device shares that array: two calls
+ * that overlap on one device (on different streams, or from two threads)
+ * race and give wrong results; calls ordered on one stream are safe.
+ */
+int64_t rs_rk45_replay_noalloc_max_n(void);
+hmat_status rs_rk45_replay_noalloc(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D,
+                                   const double* dts, int64_t n_steps, double* ckpt, int64_t ckpt_every,
+                                   void* stream);
+
 /* Bytes of device workspace rs_rk45_adjoint needs: 8 (36 n K + 31 n + 32)
  * with K = min(ckpt_every, n_steps) (-1 on bad arguments or overflow). */
 int64_t rs_rk45_adjoint_workspace_bytes(int64_t n, int64_t ckpt_every);

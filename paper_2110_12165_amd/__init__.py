@@ -308,10 +308,12 @@ class RK45:
         if self.B is not None and self.B is not self.A:
             self.B.check(stream)
 
-    def replay(self, y, D, dts, ckpt_every=0, stream=None):
+    def replay(self, y, D, dts, ckpt_every=0, stream=None, noalloc=False):
         """The integration on the frozen steps dts (rs_rk45_replay): y (and D,
         unless None) advance in place.  With ckpt_every > 0 returns the
-        checkpoints (the state before every ckpt_every-th step) for adjoint()."""
+        checkpoints (the state before every ckpt_every-th step) for adjoint().
+        noalloc: rs_rk45_replay_noalloc (the library's static scratch instead
+        of this object's workspace)."""
         torch = _torch()
         n = self.A.n
         _gpu_f64(y, (3 * n,), "y")
@@ -326,7 +328,10 @@ class RK45:
         args = (self.A._h, None if self.B is None else self.B._h, C.byref(self.params), _dptr(y),
                 None if D is None else _dptr(D), d.ctypes.data_as(C.POINTER(C.c_double)), m,
                 None if ckpt is None else _dptr(ckpt), max(ckpt_every, 1))
-        check(lib.rs_rk45_replay(*args, _dptr(self.workspace), _stream_ptr(stream)))
+        if noalloc:
+            check(lib.rs_rk45_replay_noalloc(*args, _stream_ptr(stream)))
+        else:
+            check(lib.rs_rk45_replay(*args, _dptr(self.workspace), _stream_ptr(stream)))
         self._check_handles(stream)
         return ckpt
 

@@ -102,6 +102,9 @@ SIGNATURES = {
                               C.POINTER(RsRk45State), C.c_int64, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
     "rs_rk45_replay": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p,
                                  C.POINTER(C.c_double), C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
+    "rs_rk45_replay_noalloc_max_n": (C.c_int64, []),
+    "rs_rk45_replay_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_double), C.c_int64, C.c_void_p, C.c_int64, C.c_void_p]),
     "hmat_check": (C.c_int, [C.c_void_p, C.c_void_p]),
     "rs_rk45_adjoint_workspace_bytes": (C.c_int64, [C.c_int64, C.c_int64]),
     "rs_rk45_adjoint": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_int64,

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1203,6 +1204,29 @@ void enqueue_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D
   }
 }
 
+// Scratch of rs_rk45_replay_noalloc (the workspace rs_rk45_replay takes from
+// its caller), for callers that cannot allocate.  One copy per device,
+// held until the process ends; calls on one device share it.
+constexpr int64_t kStaticScratchBytes = (int64_t)32 << 20;
+__device__ __align__(256) double scratch[kStaticScratchBytes / 8];
+
+// Device address of `scratch` on device `dev` (which must be current),
+// looked up once per device.  In host code the array's name is only a
+// stand-in: kernels get this address.
+double* static_scratch(int dev) {
+  static std::mutex mu;
+  static std::vector<void*> ptrs;
+  std::lock_guard<std::mutex> lk(mu);
+  if ((int)ptrs.size() <= dev) ptrs.resize((size_t)dev + 1, nullptr);
+  if (!ptrs[dev]) {
+    void* ptr = nullptr;
+    check_hip(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!ptr) hm::fail(HMAT_EDEVICE, "hipGetSymbolAddress(scratch) returned a null address");
+    ptrs[dev] = ptr;
+  }
+  return static_cast<double*>(ptrs[dev]);
+}
+
 }  // namespace
 
 hmat_status rs_rk45_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const double* dts,
@@ -1214,6 +1238,24 @@ hmat_status rs_rk45_replay(hmat_t A, hmat_t B, const rs_params* p, double* y, do
     if (n_steps == 0) return;
     DeviceGuard g(A->device);
     enqueue_replay(A, B, p, y, D, dts, n_steps, ckpt, ckpt_every, static_cast<double*>(workspace),
+                   static_cast<hipStream_t>(stream));
+  });
+}
+
+int64_t rs_rk45_replay_noalloc_max_n(void) { return kStaticScratchBytes / (8 * replay_doubles(1)); }
+
+hmat_status rs_rk45_replay_noalloc(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const double* dts,
+                                   int64_t n_steps, double* ckpt, int64_t ckpt_every, void* stream) {
+  return guarded([&] {
+    check_replay_args(A, B, p, dts, n_steps, ckpt_every);
+    if (!y) hm::fail(HMAT_EINVAL, "null argument");
+    if (A->H.n > rs_rk45_replay_noalloc_max_n())
+      hm::fail(HMAT_EINVAL, "n = " + std::to_string(A->H.n) + " exceeds the static scratch of " +
+                                std::to_string(kStaticScratchBytes >> 20) + " MiB (at most " +
+                                std::to_string(rs_rk45_replay_noalloc_max_n()) + " elements)");
+    if (n_steps == 0) return;
+    DeviceGuard g(A->device);
+    enqueue_replay(A, B, p, y, D, dts, n_steps, ckpt, ckpt_every, static_scratch(A->device),
                    static_cast<hipStream_t>(stream));
   });
 }
