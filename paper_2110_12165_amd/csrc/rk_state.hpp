@@ -3,6 +3,11 @@
 
 namespace hm {
 
+// Slots of the error maximum: workgroup k of the error kernel folds its
+// maximum into slot k % kErrSlots, so no single address takes every
+// workgroup's atomic; the controller takes the maximum of the slots.
+constexpr int kErrSlots = 8;
+
 // Device-resident state of the adaptive Runge-Kutta integration: every
 // kernel of an attempt reads the step from here, and the controller kernel
 // (eqs. (14)-(15)) updates it, so attempts can be replayed from a graph with
@@ -14,7 +19,7 @@ struct RkDevState {
   int ok;           // decision of the last attempt
   int halted;       // target reached: further attempts change nothing
   int pad;
-  unsigned long long err_bits;  // max relative difference, as the bits of a non-negative double
+  unsigned long long err_bits[kErrSlots];  // max relative difference, as the bits of a non-negative double
   long long log_base;           // accepted count at which the step log starts
 };
 

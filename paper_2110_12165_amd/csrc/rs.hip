@@ -15,6 +15,8 @@
 //             / (1 + eta dV/dtau)
 // The backslip loading tau_dot = -V_pl sum_j A_ij is folded into the product
 // by applying A to V - V_pl.
+#include <algorithm>
+
 #include "device_types.hpp"
 #include "rk_state.hpp"
 #include "rk_tableau.hpp"
@@ -92,26 +94,44 @@ __global__ void k_stage_slip(int64_t n, int s, const RkDevState* __restrict__ st
   x[i] = V - V_pl;
 }
 
-__global__ void k_begin(RkDevState* st) { st->err_bits = 0ull; }
+__global__ void k_begin(RkDevState* st) {
+  if (threadIdx.x < kErrSlots) st->err_bits[threadIdx.x] = 0ull;
+}
 
 // y5, and max_i |y5 - y4| / max(|y5|, 1e-300) (non-negative doubles order like
 // their bit patterns, so the maximum is an integer atomic max; NaN wins).
-__global__ __launch_bounds__(256) void k_finish(int64_t n3, RkDevState* st, const double* __restrict__ y,
-                                                const double* __restrict__ k, double* __restrict__ y5) {
-  __shared__ double part[4];
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Grid-stride over the 3n components with at most kFinishBlocks workgroups;
+// k_1 has weight 0 in both solutions of the pair and is not read.  Each
+// workgroup folds its maximum into one of the kErrSlots slots: the result
+// does not depend on the grid (a maximum is exact in any order).
+constexpr int kFinishThreads = 256;
+constexpr int kFinishBlocks = 512;
+
+__global__ __launch_bounds__(kFinishThreads) void k_finish(int64_t n3, RkDevState* st, const double* __restrict__ y,
+                                                           const double* __restrict__ k, double* __restrict__ y5) {
+  __shared__ double part[kFinishThreads / 64];
   const double dt = st->dt;
+  double c5[6], c4[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    c5[j] = dt * kB5[j];
+    c4[j] = dt * kB4[j];
+  }
   double e = 0.0;
-  if (i < n3) {
-    double v5 = y[i], v4 = y[i];
+  for (int64_t i = (int64_t)blockIdx.x * kFinishThreads + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * kFinishThreads) {
+    double v5 = y[i], v4 = v5;
+#pragma unroll
     for (int j = 0; j < 6; ++j) {
+      if (kB5[j] == 0.0 && kB4[j] == 0.0) continue;
       const double kj = k[j * n3 + i];
-      if (kB5[j] != 0.0) v5 = v5 + (dt * kB5[j]) * kj;
-      if (kB4[j] != 0.0) v4 = v4 + (dt * kB4[j]) * kj;
+      if (kB5[j] != 0.0) v5 = v5 + c5[j] * kj;
+      if (kB4[j] != 0.0) v4 = v4 + c4[j] * kj;
     }
     y5[i] = v5;
-    e = fabs(v5 - v4) / fmax(fabs(v5), 1e-300);
-    if (e != e) e = __longlong_as_double(0x7ff8000000000000ll);
+    double ei = fabs(v5 - v4) / fmax(fabs(v5), 1e-300);
+    if (ei != ei) ei = __longlong_as_double(0x7ff8000000000000ll);
+    e = (ei != ei || ei > e) ? ei : e;
   }
   for (int d = 32; d >= 1; d >>= 1) {
     const double o = __shfl_xor(e, d, 64);
@@ -122,8 +142,8 @@ __global__ __launch_bounds__(256) void k_finish(int64_t n3, RkDevState* st, cons
   __syncthreads();
   if (threadIdx.x == 0) {
     double m = part[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) m = (part[w] != part[w] || part[w] > m) ? part[w] : m;
-    atomicMax(&st->err_bits, (unsigned long long)__double_as_longlong(m));
+    for (int w = 1; w < kFinishThreads / 64; ++w) m = (part[w] != part[w] || part[w] > m) ? part[w] : m;
+    atomicMax(&st->err_bits[blockIdx.x % kErrSlots], (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -136,7 +156,9 @@ __global__ void k_control(RkDevState* st) {
     st->ok = 0;
     return;
   }
-  const double err = __longlong_as_double((long long)st->err_bits);
+  unsigned long long bits = st->err_bits[0];
+  for (int q = 1; q < kErrSlots; ++q) bits = st->err_bits[q] > bits ? st->err_bits[q] : bits;
+  const double err = __longlong_as_double((long long)bits);
   const double r = err / st->eps;
   const double dt = st->dt;
   const bool finite = r == r && r != __longlong_as_double(0x7ff0000000000000ll);
@@ -188,14 +210,15 @@ hipError_t launch_rk_stage_slip(int64_t n, int s, const RkDevState* st, double d
 }
 
 hipError_t launch_rk_begin(RkDevState* st, hipStream_t strm) {
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, strm, st);
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kErrSlots), 0, strm, st);
   return hipGetLastError();
 }
 
 hipError_t launch_rk_finish_control(int64_t n3, RkDevState* st, const double* y, const double* k, double* y5,
                                     hipStream_t strm) {
-  const int bs = 256;
-  hipLaunchKernelGGL(k_finish, dim3((unsigned)((n3 + bs - 1) / bs)), dim3(bs), 0, strm, n3, st, y, k, y5);
+  const int64_t blocks = std::min<int64_t>(kFinishBlocks, (n3 + kFinishThreads - 1) / kFinishThreads);
+  hipLaunchKernelGGL(k_finish, dim3((unsigned)std::max<int64_t>(1, blocks)), dim3(kFinishThreads), 0, strm, n3, st, y,
+                     k, y5);
   hipLaunchKernelGGL(k_control, dim3(1), dim3(1), 0, strm, st);
   return hipGetLastError();
 }
