@@ -5,9 +5,12 @@ Tolerances from the arithmetic: FP32 storage (unit roundoff 6e-8) and FP32
 accumulation on MFMA over up to a few thousand inputs per row:
 * BF16x6 (three bf16 parts represent each FP32 operand exactly; the dropped
   cross products are O(2^-24)): relative error <= 2e-5, as the FP32 path;
-* BF16x3 (two parts, 16 significant bits; dropped terms O(2^-16) per
-  product, about 4.6e-5 relative, amplified by cancellation in the row
-  sums): relative error <= 1e-3.
+* BF16x3 (two parts, 16 significant bits: each operand and each stored
+  intermediate value within 2^-17 relative, so a term within about
+  3 * 2^-17 = 2.3e-5 of its size, and sums of many such terms with mixed
+  rounding far closer): relative error <= 5e-5 on log-uniform members; on
+  the degenerate sizes with signed members, 4 * 2^-17 times the
+  cancellation factor |A| |X| / |A X| of the case.
 """
 import numpy as np
 import pytest
@@ -52,7 +55,11 @@ def case(request):
     Hg.close()
 
 
-@pytest.mark.parametrize("mode,tol", [("x6", 2e-5), ("x3", 1e-3)])
+# BF16x3 keeps 16 significant bits of each operand and of each stored
+# intermediate value (two bf16 parts: relative error <= 2^-17 each), so a
+# term carries at most ~3 * 2^-17 = 2.3e-5 of its size and a sum of many
+# terms of mixed rounding far less: 5e-5 bounds it (measured 3e-6 to 5e-6).
+@pytest.mark.parametrize("mode,tol", [("x6", 2e-5), ("x3", 5e-5)])
 def test_ensemble_parity(case, mode, tol):
     torch, hm, name, f, H, Hg = case
     dev = torch.device("cuda:0")
@@ -107,7 +114,10 @@ def test_ensemble_degenerate_sizes(groups):
         Hg = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, leaf=leaf, prec="f32", kernel="split", max_nrhs=64,
                               mm_groups=groups)
         X = rng.standard_normal((f.n, 3))
-        for mode, tol in (("x6", 2e-5), ("x3", 1e-3)):
+        # few terms per row and signed members: the BF16x3 bound per term
+        # (3 * 2^-17) times the cancellation in A X, with room
+        kappa = np.linalg.norm(np.abs(A) @ np.abs(X)) / np.linalg.norm(A @ X)
+        for mode, tol in (("x6", 2e-5), ("x3", 4 * 2.0 ** -17 * kappa)):
             Y = Hg.matmat(torch.tensor(X, device=dev), mode=mode).cpu().numpy()
             assert rel(Y, A @ X) <= tol, (nx, ny, leaf, mode)
         Hg.close()

@@ -4,8 +4,9 @@ with triangles: the shear matrix A and the normal matrix B (nonzero here).
 * N = 1920: GPU products (FP64 and FP32 storage, A and B) against the dense
   product of the library's closed-form entries (all rows) and against rows
   of the oracle's independent cubature (three rows);
-* N = 21000 (the paper-scale triangle mesh): FP32-batched against FP64-plain
-  and against exact rows evaluated one by one;
+* N = 21000 (the paper-scale triangle mesh): FP32-batched against FP64-plain,
+  and both against rows of the oracle's cubature (eight rows of A and of B,
+  sources spread over processes);
 * N = 96: forced-decision RK45 with sigma evolving through B, against the
   oracle's integration on oracle-built dense matrices.
 
@@ -16,7 +17,7 @@ RK45 as in test_gpu_rs (1e-8 after the steps).
 import numpy as np
 import pytest
 
-from _util import rel, say
+from _util import oracle_triangle_rows, rel, say
 from oracle import friction as fr
 from oracle import rk45
 from oracle.triangles import TriangleGeometry
@@ -84,7 +85,7 @@ def test_paper_scale_triangles():
     x = loguniform_rates(f.n, w["seed"])
     xd = torch.tensor(x, device="cuda:0")
     rows = np.random.default_rng(1).choice(f.n, 8, replace=False)
-    cols = np.arange(f.n)
+    oracle_rows = oracle_triangle_rows(f.verts, f.slip_dir, rows)      # (A rows, B rows)
     for component in (0, 1):
         H32 = _build(hm, f, w, component, "f32", "split")
         y32 = H32.matvec(xd).cpu().numpy()
@@ -97,9 +98,11 @@ def test_paper_scale_triangles():
             f"rel FP32 vs FP64 {rel(y32, y64):.2e}")
         assert info["n_lr"] > 0
         assert rel(y32, y64) <= 2e-5
-        exact = np.array([hm.kernel_entries(f.verts, f.slip_dir, MU, NU, np.full(f.n, i), cols, component) @ x
-                          for i in rows])
+        exact = oracle_rows[component] @ x
+        say(f"   {'AB'[component]}: FP64 product vs the oracle's rows (cubature): "
+            f"{np.max(np.abs(y64[rows] - exact)) / np.max(np.abs(y64)):.2e} of the largest entry")
         assert np.max(np.abs(y64[rows] - exact)) <= 1e-5 * np.max(np.abs(y64))
+        assert np.max(np.abs(y32[rows] - exact)) <= 1e-5 * np.max(np.abs(y64))
 
 
 def test_rk45_with_normal_stress_against_oracle():
@@ -193,11 +196,14 @@ def test_overlapped_a_and_b_products_are_reproducible():
     HB.close()
 
 
+_ORACLE_ROWS = {}   # oracle cubature rows, shared by the parametrised cases
+
+
 @pytest.mark.parametrize("component", [0, 1])
 def test_paper_scale_ensemble_product(component):
     """The 64-member ensemble product on the 21000-triangle fault (A and B),
     both wave-group settings, against the FP64 plain product of the same
-    mesh and exact rows from the entries."""
+    mesh, whose rows are checked against the oracle's (cubature)."""
     import torch
 
     import paper_2110_12165_amd as hm
@@ -211,8 +217,10 @@ def test_paper_scale_ensemble_product(component):
                     for c in range(X.shape[1])], axis=1)
     H64.close()
     rows = np.random.default_rng(2).choice(f.n, 4, replace=False)
-    exact = np.array([hm.kernel_entries(f.verts, f.slip_dir, MU, NU, np.full(f.n, i), np.arange(f.n), component)
-                      for i in rows]) @ X
+    key = (name, tuple(int(i) for i in rows))
+    if key not in _ORACLE_ROWS:
+        _ORACLE_ROWS[key] = oracle_triangle_rows(f.verts, f.slip_dir, rows)
+    exact = _ORACLE_ROWS[key][component] @ X
     assert np.max(np.abs(ref[rows] - exact)) <= 1e-5 * np.max(np.abs(ref))
     Xd = torch.tensor(X, device=dev)
     for groups in (1, 2):
