@@ -15,7 +15,8 @@ construction (host and device), autotuner, size and lattice sweeps, a
 (curved thrust of 21000 triangles and the N = 122880 fault), the nonplanar
 fault (A and B products, RK45 with sigma evolving), the 64-member ensemble
 integration and the adjoint gradient on the curved thrust (A and B), and
-the oracle's CPU rate on a bounded sample.
+the oracle's CPU rates on bounded samples (block loop, sparse form, exact
+FFT product, Runge-Kutta steps).
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline]
 """
@@ -98,48 +99,127 @@ def time_products(torch, H, x, y, steps, warmup):
     return max(region, 1e-9), per, wall
 
 
+def _timed(fn, seconds):
+    """Seconds per call of fn over about `seconds` (after one untimed call)."""
+    fn()
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        out = fn()
+        reps += 1
+        el = time.perf_counter() - t0
+        if el > seconds:
+            return el / reps, reps, el, out
+
+
 def cpu_baseline(f, w, x, y_gpu):
-    """Oracle H-matrix product timed on a bounded sample: the complete
-    lattice block-rows 0 and 15 (2 of 32, 7680 of 122880 rows), built by the
-    oracle's own ACA, applied repeatedly for about 15 s with one BLAS thread;
-    scaled to full products by the row fraction."""
+    """The oracle timed on the host cores, on bounded samples:
+
+    * the H-matrix product on the complete lattice block-rows 0 and 15 (2 of
+      32, 7680 of 122880 rows), built by the oracle's own ACA, scaled to
+      full products by the row fraction: the block loop with all host
+      threads for BLAS (the headline value) and with one thread, and the
+      sparse form (SciPy CSR) with one thread and with row chunks on all
+      host threads;
+    * the exact product of the whole matrix by FFT (the dense definition,
+      N = 122880; NumPy's FFT runs on one thread);
+    * the oracle's Runge-Kutta integration on the 2048-element fault
+      (steps per second, block-loop product)."""
     from threadpoolctl import threadpool_limits
 
+    from oracle import friction as fr
+    from oracle import rk45 as ork
+    from oracle.dense import fft_grid_product
     from oracle.greens import CoplanarRectGeometry
     from oracle.hmatrix import HMatrix as OracleH
+    from oracle.hmatrix import SparseHMatrix
+    from synth import WORKLOADS, config_fault, friction_params
     from synth.faults import MU, NU
 
+    threads = len(os.sched_getaffinity(0))
     g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
     rows_sel = (0, 15)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=threads):
         H = OracleH.build(g, w["leaf"], w["eta"], w["aca_eps"], w["lattice"], lattice_rows=rows_sel)
-        build_s = time.perf_counter() - t0
-        H.matvec(x)
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            y = H.matvec(x)
-            reps += 1
-            el = time.perf_counter() - t0
-            if el > 15.0:
-                break
-    per_sample = el / reps
+    build_s = time.perf_counter() - t0
     lat_rows = H.lattice_row_ranges(rows_sel)
     nrows = sum(e - s for s, e in lat_rows)
     scale = f.n / nrows
+    forms = {}
+    with threadpool_limits(limits=threads):
+        per, reps, el, y = _timed(lambda: H.matvec(x), 10.0)
+    forms["block_loop_all_threads"] = dict(matvec_per_s=1.0 / (per * scale), threads=threads, reps=reps, s=el)
+    with threadpool_limits(limits=1):
+        per, reps, el, _ = _timed(lambda: H.matvec(x), 10.0)
+    forms["block_loop_1_thread"] = dict(matvec_per_s=1.0 / (per * scale), threads=1, reps=reps, s=el)
+    for th in (1, threads):
+        S = SparseHMatrix(H, threads=th)
+        with threadpool_limits(limits=1):
+            per, reps, el, _ = _timed(lambda: S.matvec(x), 5.0)
+        S.close()
+        forms[f"sparse_csr_{'1_thread' if th == 1 else 'all_threads'}"] = dict(
+            matvec_per_s=1.0 / (per * scale), threads=th, reps=reps, s=el)
+    per, reps, el, _ = _timed(lambda: fft_grid_product(f.nx, f.ny, f.h, f.slip, MU, NU, x), 5.0)
+    forms["exact_fft_full_matrix"] = dict(matvec_per_s=1.0 / per, threads=1, reps=reps, s=el,
+                                          note="the dense definition y = A x, whole matrix, no row sampling")
+    # oracle Runge-Kutta steps on the 2048-element fault (its own H-matrix)
+    w0 = WORKLOADS["planar64x32"]
+    f0 = config_fault("planar64x32")
+    p0 = friction_params(f0)
+    g0 = CoplanarRectGeometry(f0.verts, f0.slip_dir, MU, NU)
+    with threadpool_limits(limits=threads):
+        H0 = OracleH.build(g0, w0["leaf"], w0["eta"], w0["aca_eps"], w0["lattice"])
+        y0 = fr.initial_state(10.0 ** (-12.0 + 3.0 * np.random.default_rng(0).random(f0.n)), p0, p0["sigma"])
+        t0 = time.perf_counter()
+        run = ork.integrate(lambda z: fr.rhs(z, p0, H0.matvec), y0, 1.0, 60)
+        el = time.perf_counter() - t0
+    forms["rk45_planar64x32"] = dict(steps_per_s=60 / el, attempts=len(run["log"]), threads=threads, s=el,
+                                     note="N = 2048, 60 accepted steps from steady state, block-loop products")
+    head = forms["block_loop_all_threads"]
     # compare the oracle's sampled rows with the GPU product on the same rows
     idx = np.concatenate([H.perm[s:e] for s, e in lat_rows])
     err = float(np.linalg.norm(y[idx] - y_gpu[idx]) / np.linalg.norm(y[idx]))
     cpu = open("/proc/cpuinfo").read()
     model = next((l.split(":", 1)[1].strip() for l in cpu.splitlines() if l.startswith("model name")), "unknown")
+    log("[bench] cpu baseline: " + ", ".join(
+        f"{k} {v.get('matvec_per_s', v.get('steps_per_s')):.2f}" for k, v in forms.items()))
     return {
-        "value": 1.0 / (per_sample * scale), "unit": "matvec/s", "cores": 1, "kind": "oracle",
-        "sample": (f"oracle FP64 H-matrix product (NumPy block loop, 1 BLAS thread) over lattice block-rows "
-                   f"{list(rows_sel)} = {nrows} of {f.n} rows, {reps} products in {el:.1f} s, scaled by "
-                   f"{scale:.1f}; oracle build of the sample {build_s:.1f} s (untimed)"),
-        "cpu_model": model, "host_threads_available": len(os.sched_getaffinity(0)),
+        "value": head["matvec_per_s"], "unit": "matvec/s", "cores": threads, "kind": "oracle",
+        "sample": (f"oracle FP64 H-matrix product (NumPy block loop, BLAS on {threads} threads) over lattice "
+                   f"block-rows {list(rows_sel)} = {nrows} of {f.n} rows, {head['reps']} products in "
+                   f"{head['s']:.1f} s, scaled by {scale:.1f}; oracle build of the sample {build_s:.1f} s "
+                   f"(untimed); the other forms under 'forms'"),
+        "forms": forms,
+        "cpu_model": model, "host_threads_available": threads,
         "sample_rel_err_gpu_f32_vs_oracle": err,
     }
+
+
+def _timed_share(torch, hm, rk, p, phi, tau, n_steps, dev):
+    """The products' share of the GPU time of the integration, measured in
+    the run itself: the same n_steps from the same initial state again,
+    with wall-clock stamps around each stage's products and each attempt
+    (rs_rk45_run_timed)."""
+    n = phi.shape[0]
+    rk.state.t, rk.state.dt, rk.state.accepted, rk.state.rejected = 0.0, 1.0, 0, 0
+    y = torch.tensor(np.concatenate([phi, tau, p["sigma"]]), device=dev)
+    D = torch.zeros(n, dtype=torch.float64, device=dev)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        rk.run_timed(y, D, 2, use_graph=True, stream=s)    # capture + warm-up
+        rk.state.t, rk.state.dt, rk.state.accepted, rk.state.rejected = 0.0, 1.0, 0, 0
+        y.copy_(torch.tensor(np.concatenate([phi, tau, p["sigma"]]), device=dev))
+        D.zero_()
+        s.synchronize()
+        t0 = time.perf_counter()
+        tm = rk.run_timed(y, D, n_steps, use_graph=True, stream=s)
+        s.synchronize()
+        tm["wall_s"] = time.perf_counter() - t0
+    tm["note"] = ("device wall-clock stamps before and after each stage's products and around each attempt, "
+                  "in a second run of the same steps from the same state; hmvm_share = product_ms / attempt_ms")
+    log(f"[bench] measured product share: {tm['product_ms']:.1f} of {tm['attempt_ms']:.1f} ms of GPU time "
+        f"({100 * tm['hmvm_share']:.1f} %), {tm['attempts']} attempts")
+    return tm
 
 
 def rk45_run(torch, hm, f, w, x_np, n_steps):
@@ -171,9 +251,8 @@ def rk45_run(torch, hm, f, w, x_np, n_steps):
         s.synchronize()
         wall = time.perf_counter() - t0
     attempts = (rk.state.accepted - acc0) + (rk.state.rejected - rej0)
-    xd = torch.tensor(x_np, device=dev)
-    prof = H.profile(xd, torch.empty_like(xd), reps=20)
-    hmvm = 6 * attempts * prof["ms_product"] * 1e-3
+    t_end, dt_end = rk.t, rk.dt
+    share = _timed_share(torch, hm, rk, p, phi, tau, n_steps, dev)
     H.close()
     # FP32 against FP64 factors on the whole run: each with its own step
     # control from the same initial state; the simulated time at which the
@@ -207,11 +286,11 @@ def rk45_run(torch, hm, f, w, x_np, n_steps):
         log(f"[bench] rk45 onset of the first event (max V >= 1e-3 m/s): FP32 t = {t32:.6e} s after {k32} steps, "
             f"FP64 t = {t64:.6e} s after {k64} steps (relative {ev['t_rel_diff']:.1e}); slip then differs by "
             f"{ev['slip_rel_diff']:.1e} of its largest value")
-    log(f"[bench] rk45: {n_steps} steps, {attempts} attempts in {wall:.3f} s, simulated {rk.t - t_sim0:.3e} s")
+    log(f"[bench] rk45: {n_steps} steps, {attempts} attempts in {wall:.3f} s, simulated {t_end - t_sim0:.3e} s")
     return {"accepted_steps": n_steps, "attempts": attempts, "wall_s": wall,
             "steps_per_s": n_steps / wall, "attempts_per_s": attempts / wall,
-            "simulated_s": rk.t - t_sim0, "simulated_s_per_wall_s": (rk.t - t_sim0) / wall,
-            "hmvm_share": hmvm / wall, "dt_last": rk.dt,
+            "simulated_s": t_end - t_sim0, "simulated_s_per_wall_s": (t_end - t_sim0) / wall,
+            "hmvm_share": share["hmvm_share"], "hmvm_share_measurement": share, "dt_last": dt_end,
             "event_onset_f32_vs_f64": ev,
             "note": "Cash-Karp RK45, eps_RK 1e-4, graph-replayed attempts; friction a=0.010, b=0.015/0.005, "
                     "d_c=0.01 m, sigma=50 MPa, V_pl=1e-9 m/s; start from steady state at the benchmark slip rates"}
@@ -452,11 +531,14 @@ def nonplanar_rk(torch, hm, f, w, n_steps):
         wall = time.perf_counter() - t0
     attempts = (rk.state.accepted - acc0) + (rk.state.rejected - rej0)
     sig = y[2 * f.n:].cpu().numpy()
+    t_end, dt_end = rk.t, rk.dt
+    share = _timed_share(torch, hm, rk, p, phi, tau, n_steps, dev)
     HA.close()
     HB.close()
     out = {"accepted_steps": n_steps, "attempts": attempts, "wall_s": wall, "steps_per_s": n_steps / wall,
-           "simulated_s": rk.t - t_sim0, "simulated_s_per_wall_s": (rk.t - t_sim0) / wall, "dt_last": rk.dt,
-           "sigma_change_max_pa": float(np.max(np.abs(sig - p["sigma"])))}
+           "simulated_s": t_end - t_sim0, "simulated_s_per_wall_s": (t_end - t_sim0) / wall, "dt_last": dt_end,
+           "sigma_change_max_pa": float(np.max(np.abs(sig - p["sigma"]))),
+           "hmvm_share": share["hmvm_share"], "hmvm_share_measurement": share}
     log(f"[bench] nonplanar rk45 (A and B): {n_steps} steps, {attempts} attempts in {wall:.3f} s, simulated "
         f"{out['simulated_s']:.3e} s; normal stress moved by up to {out['sigma_change_max_pa']:.3e} Pa")
     return out
@@ -758,7 +840,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 storage, f64 accumulate",
         "data": "synthetic",
         "config": {
             "workload": WORKLOAD, "N": f.n,

@@ -277,6 +277,11 @@ hmat_status hmat_info(hmat_t h, hmat_stats* out);
  * own blocks and keep the fastest.  Synchronises the stream.  Products before and after give
  * results equal to within rounding (the summation order of a row can
  * change with the schedule).  reps: timed products per candidate (>= 1).
+ * The choice is remembered for the life of the process, keyed by the block
+ * list, the storage and schedule options and the device model: a later
+ * call on a handle with the same key re-lays it out with that choice
+ * without timing.  The choices timed at creation (the small-matrix layout,
+ * the ensemble wave groups) are remembered the same way.
  */
 hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream);
 
@@ -358,7 +363,7 @@ typedef struct {
  * everywhere: B's own stream is no exception). */
 
 /* Bytes of device workspace rs_rk45_attempt needs for n elements:
- * 8 * (28 n + 32).  n < 0 returns -1. */
+ * 8 * (28 n + 288).  n < 0 returns -1. */
 int64_t rs_rk45_workspace_bytes(int64_t n);
 
 /*
@@ -396,6 +401,26 @@ hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, d
 hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                         rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, double* dt_log,
                         int32_t use_graph, void* stream);
+
+/* GPU time of a timed run (rs_rk45_run_timed), from the device wall clock. */
+typedef struct {
+  double product_ms;       /* summed time of the stages' products (with B: the pair, side by side) */
+  double attempt_ms;       /* summed time of the attempts, first kernel to last */
+  int64_t attempts;        /* attempts launched */
+} rs_rk45_timing;
+
+/*
+ * rs_rk45_run_timed — rs_rk45_run with the products' share of the GPU time
+ * measured in the run itself: each attempt (graph-captured like
+ * rs_rk45_run's, cached separately) also launches one-thread kernels that
+ * read the device wall clock at its start and end and before and after each
+ * stage's products, and sum the intervals on the device; *timing receives
+ * the totals.  The stamps add about one small kernel each (13 per attempt)
+ * to the run.  Same arguments, state and results as rs_rk45_run otherwise.
+ */
+hmat_status rs_rk45_run_timed(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                              rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, double* dt_log,
+                              int32_t use_graph, void* stream, rs_rk45_timing* timing);
 
 /* rs_rk45_step — rs_rk45_run for one accepted step, without a graph. */
 hmat_status rs_rk45_step(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,

@@ -308,6 +308,22 @@ class RK45:
         if self.B is not None and self.B is not self.A:
             self.B.check(stream)
 
+    def run_timed(self, y, D, n_accept, max_attempts=0, use_graph=True, stream=None, dt_log=None):
+        """run() with the products' share of the GPU time measured inside the
+        run (rs_rk45_run_timed).  Returns dict(product_ms, attempt_ms,
+        attempts, hmvm_share)."""
+        self._check(y, D)
+        if dt_log is not None and (dt_log.dtype != _torch().float64 or not dt_log.is_cuda
+                                   or dt_log.numel() < n_accept or not dt_log.is_contiguous()):
+            raise ValueError("dt_log must be a contiguous float64 GPU tensor of at least n_accept entries")
+        tm = _lib.RsRk45Timing()
+        check(_lib.load().rs_rk45_run_timed(self.A._h, None if self.B is None else self.B._h, C.byref(self.params),
+                                            _dptr(y), _dptr(D), _dptr(self.workspace), C.byref(self.state),
+                                            n_accept, max_attempts, None if dt_log is None else _dptr(dt_log),
+                                            1 if use_graph else 0, _stream_ptr(stream), C.byref(tm)))
+        share = tm.product_ms / tm.attempt_ms if tm.attempt_ms > 0 else float("nan")
+        return dict(product_ms=tm.product_ms, attempt_ms=tm.attempt_ms, attempts=tm.attempts, hmvm_share=share)
+
     def replay(self, y, D, dts, ckpt_every=0, stream=None, noalloc=False):
         """The integration on the frozen steps dts (rs_rk45_replay): y (and D,
         unless None) advance in place.  With ckpt_every > 0 returns the

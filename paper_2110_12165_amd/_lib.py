@@ -64,6 +64,10 @@ class RsRk45State(C.Structure):
                 ("accepted", C.c_int64), ("rejected", C.c_int64)]
 
 
+class RsRk45Timing(C.Structure):
+    _fields_ = [("product_ms", C.c_double), ("attempt_ms", C.c_double), ("attempts", C.c_int64)]
+
+
 class RsEnsParams(C.Structure):
     _fields_ = [("n", C.c_int64), ("members", C.c_int32), ("mode", C.c_int32), ("V0", C.c_double),
                 ("f0", C.c_double), ("eta_rad", C.c_double), ("V_pl", C.c_double), ("a", C.c_void_p),
@@ -100,6 +104,9 @@ SIGNATURES = {
                                   C.POINTER(RsRk45State), C.c_int32, C.c_void_p]),
     "rs_rk45_run": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p, C.c_void_p,
                               C.POINTER(RsRk45State), C.c_int64, C.c_int64, C.c_void_p, C.c_int32, C.c_void_p]),
+    "rs_rk45_run_timed": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.POINTER(RsRk45State), C.c_int64, C.c_int64, C.c_void_p, C.c_int32,
+                                    C.c_void_p, C.POINTER(RsRk45Timing)]),
     "rs_rk45_replay": (C.c_int, [C.c_void_p, C.c_void_p, C.POINTER(RsParams), C.c_void_p, C.c_void_p,
                                  C.POINTER(C.c_double), C.c_int64, C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p]),
     "rs_rk45_replay_noalloc_max_n": (C.c_int64, []),

@@ -2,6 +2,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <atomic>
 #include <cstdint>
 #include <cmath>
@@ -163,10 +165,11 @@ struct hmat_s {
   }
   // captured Runge-Kutta attempts (rs_rk45_run, rs_ens_rk45_run), each keyed
   // by everything it reads
-  GraphCache rk_cache, ens_cache;
+  GraphCache rk_cache, rk_timed_cache, ens_cache;
 
   void drop_graph() {
     rk_cache.drop();
+    rk_timed_cache.drop();
     ens_cache.drop();
   }
 
@@ -419,6 +422,61 @@ constexpr int32_t kSmallWavesP2 = 4;
 constexpr int32_t kDefaultUnitKiB = 256;
 constexpr int kMMTuneReps = 5;  // timed ensemble products per mode and wave-group count
 
+// Choices made by timing (the small-matrix layout at creation, the ensemble
+// wave groups, hmat_autotune's schedule), remembered for the life of the
+// process: a handle whose block list, storage, options and device model
+// match one timed before takes the same choice without timing again.  The
+// key is a 64-bit FNV-1a hash of all of these (a collision only costs a
+// choice timed for another matrix: results stay correct either way).
+enum TuneKind { kTuneSmallLayout = 1, kTuneMMGroups = 2, kTuneAutotune = 3 };
+
+struct TuneCache {
+  std::mutex mu;
+  std::map<std::pair<uint64_t, int>, std::array<int32_t, 4>> picks;
+};
+TuneCache& tune_cache() {
+  static TuneCache c;
+  return c;
+}
+
+uint64_t fnv1a(uint64_t h, const void* p, size_t bytes) {
+  const unsigned char* c = static_cast<const unsigned char*>(p);
+  for (size_t i = 0; i < bytes; ++i) h = (h ^ c[i]) * 1099511628211ull;
+  return h;
+}
+
+uint64_t tune_key(const hmat_s* h) {
+  uint64_t k = 1469598103934665603ull;
+  const hm::HostMatrix& H = h->H;
+  k = fnv1a(k, &H.n, sizeof(H.n));
+  k = fnv1a(k, H.desc.data(), H.desc.size() * sizeof(int64_t));
+  k = fnv1a(k, H.perm.data(), H.perm.size() * sizeof(int32_t));
+  const int32_t o[7] = {h->opts.prec, h->opts.wg_waves, h->opts.wg_waves_p1, h->opts.unit_kib,
+                        h->opts.max_nrhs > 0, h->opts.mm_groups, h->opts.kernel};
+  k = fnv1a(k, o, sizeof(o));
+  hipDeviceProp_t prop{};
+  if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) {
+    k = fnv1a(k, prop.gcnArchName, strnlen(prop.gcnArchName, sizeof(prop.gcnArchName)));
+    k = fnv1a(k, &prop.multiProcessorCount, sizeof(prop.multiProcessorCount));
+  }
+  return k;
+}
+
+bool tune_lookup(uint64_t key, int kind, std::array<int32_t, 4>& out) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  auto it = c.picks.find({key, kind});
+  if (it == c.picks.end()) return false;
+  out = it->second;
+  return true;
+}
+
+void tune_store(uint64_t key, int kind, const std::array<int32_t, 4>& v) {
+  TuneCache& c = tune_cache();
+  std::lock_guard<std::mutex> lk(c.mu);
+  c.picks[{key, kind}] = v;
+}
+
 // Wave groups of the ensemble product.  Two groups per slice halve the
 // path of each workgroup and the workgroups resident per compute unit;
 // which wins depends on the unit sizes and counts in a way no simple rule
@@ -433,6 +491,18 @@ constexpr int kMMTuneReps = 5;  // timed ensemble products per mode and wave-gro
 void tune_mm(hmat_s* h, hipStream_t s) {
   if (h->opts.mm_groups) {
     for (auto& m : h->mm_groups) m[0] = m[1] = h->opts.mm_groups;
+    ++h->gen;
+    return;
+  }
+  // the groups depend on the layout the handle has now: its schedule joins the key
+  const uint64_t key = fnv1a(tune_key(h), &h->batched.wg_waves, sizeof(int32_t)) ^
+                       (uint64_t)(uint32_t)h->batched.wg_waves_p1 * 0x9e3779b97f4a7c15ull;
+  std::array<int32_t, 4> hit{};
+  if (tune_lookup(key, kTuneMMGroups, hit)) {
+    h->mm_groups[0][0] = hit[0];
+    h->mm_groups[0][1] = hit[1];
+    h->mm_groups[1][0] = hit[2];
+    h->mm_groups[1][1] = hit[3];
     ++h->gen;
     return;
   }
@@ -469,6 +539,7 @@ void tune_mm(hmat_s* h, hipStream_t s) {
     }
     for (int p = 0; p < 2; ++p) h->mm_groups[m][p] = ms[1][p] < ms[0][p] ? 2 : 1;
   }
+  tune_store(key, kTuneMMGroups, {h->mm_groups[0][0], h->mm_groups[0][1], h->mm_groups[1][0], h->mm_groups[1][1]});
   ++h->gen;
 }
 
@@ -560,17 +631,24 @@ hmat_t create_handle(hm::HostMatrix&& H, const hmat_opts& o, hipStream_t s, bool
       if (!o.wg_waves) cands.push_back({kSmallWavesP2, kDefaultWavesP1, 1});
       if (o.max_nrhs > 0) cands = {{wg, kDefaultWavesP1, 0}, {wg, kSmallWavesP1, 0}};
       double best = 1e300;
-      Cand pick = cands[0], cur{-1, -1, -1};
-      for (const Cand& c : cands) {
-        h->drop_batched();
-        h->split_mode = c.split;
-        h->setup_batched_any(c.wg, ub, c.wg1, s);
-        cur = c;
-        const double ms = h->time_product(s, kSmallTuneReps);
-        if (ms < best) {
-          best = ms;
-          pick = c;
+      Cand pick = cands[0], cur{wg, wg1, h->split_mode};
+      const uint64_t key = tune_key(h.get());
+      std::array<int32_t, 4> hit{};
+      if (tune_lookup(key, kTuneSmallLayout, hit)) {
+        pick = {hit[0], hit[1], hit[2]};
+      } else {
+        for (const Cand& c : cands) {
+          h->drop_batched();
+          h->split_mode = c.split;
+          h->setup_batched_any(c.wg, ub, c.wg1, s);
+          cur = c;
+          const double ms = h->time_product(s, kSmallTuneReps);
+          if (ms < best) {
+            best = ms;
+            pick = c;
+          }
         }
+        tune_store(key, kTuneSmallLayout, {pick.wg, pick.wg1, pick.split, 0});
       }
       if (pick.wg != cur.wg || pick.wg1 != cur.wg1 || pick.split != cur.split) {
         h->drop_batched();
@@ -838,27 +916,36 @@ hmat_status hmat_autotune(hmat_t h, int32_t reps, void* stream) {
       check_hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime");
       return (double)ms / reps;
     };
-    double best = h->has_plain ? time_it(HMAT_KERNEL_PLAIN) : 1e300;
     int32_t best_k = h->has_plain ? HMAT_KERNEL_PLAIN : h->kernel, best_w = h->opts.wg_waves,
             best_u = kDefaultUnitKiB;
     int32_t best_w1 = h->opts.wg_waves_p1;
     const int32_t saved_kernel = h->kernel;
-    for (int32_t k : {HMAT_KERNEL_BATCHED_SPLIT, HMAT_KERNEL_BATCHED_PERSISTENT})
-      for (int32_t wg : {4, 8, 16})
-        for (int32_t wg1 : {4, 8, 16}) {
-          if (k == HMAT_KERNEL_BATCHED_PERSISTENT && wg1 != wg) continue;
-          h->drop_batched();
-          h->kernel = k;
-          h->setup_batched_any(wg, (int64_t)kDefaultUnitKiB * 1024, wg1, s);
-          const double t = time_it(k);
-          if (t < best) {
-            best = t;
-            best_k = k;
-            best_w = wg;
-            best_w1 = wg1;
-            best_u = kDefaultUnitKiB;
+    const uint64_t key = tune_key(h) ^ (uint64_t)h->has_plain;
+    std::array<int32_t, 4> hit{};
+    if (tune_lookup(key, kTuneAutotune, hit)) {
+      best_k = hit[0];
+      best_w = hit[1];
+      best_w1 = hit[2];
+    } else {
+      double best = h->has_plain ? time_it(HMAT_KERNEL_PLAIN) : 1e300;
+      for (int32_t k : {HMAT_KERNEL_BATCHED_SPLIT, HMAT_KERNEL_BATCHED_PERSISTENT})
+        for (int32_t wg : {4, 8, 16})
+          for (int32_t wg1 : {4, 8, 16}) {
+            if (k == HMAT_KERNEL_BATCHED_PERSISTENT && wg1 != wg) continue;
+            h->drop_batched();
+            h->kernel = k;
+            h->setup_batched_any(wg, (int64_t)kDefaultUnitKiB * 1024, wg1, s);
+            const double t = time_it(k);
+            if (t < best) {
+              best = t;
+              best_k = k;
+              best_w = wg;
+              best_w1 = wg1;
+              best_u = kDefaultUnitKiB;
+            }
           }
-        }
+      tune_store(key, kTuneAutotune, {best_k, best_w, best_w1, 0});
+    }
     h->kernel = saved_kernel;
     h->drop_batched();
     h->kernel = best_k;
@@ -947,7 +1034,7 @@ hmat_status rs_rhs(hmat_t A, hmat_t B, const rs_params* p, const double* y, doub
   });
 }
 
-int64_t rs_rk45_workspace_bytes(int64_t n) { return n < 0 ? -1 : 8 * (28 * n + 32); }
+int64_t rs_rk45_workspace_bytes(int64_t n) { return n < 0 ? -1 : 8 * (28 * n + hm::kRkStateDoubles); }
 
 namespace {
 
@@ -972,7 +1059,7 @@ RkWs rk_workspace(void* workspace, int64_t n) {
 
 void check_rk_args(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                    const rs_rk45_state* st) {
-  static_assert(sizeof(hm::RkDevState) <= 32 * sizeof(double), "device state must fit the workspace tail");
+  static_assert(sizeof(hm::RkDevState) <= hm::kRkStateDoubles * sizeof(double), "device state must fit the workspace tail");
   if (!A || !p || !y || !D || !workspace || !st) hm::fail(HMAT_EINVAL, "null argument");
   if (!A->on_device || (B && !B->on_device)) hm::fail(HMAT_ESTATE, "handle holds host blocks only");
   if (p->n != A->H.n || (B && B->H.n != A->H.n)) hm::fail(HMAT_EINVAL, "n does not match the handles");
@@ -1024,8 +1111,9 @@ void with_pair(hmat_t A, hmat_t B, hipStream_t s, FA&& fa, FB&& fb) {
 
 // Enqueue one attempt: every kernel reads the step from the device state.
 void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, const RkWs& w, double* dt_log,
-                     hipStream_t s) {
+                     hipStream_t s, bool timed = false) {
   const int64_t n = A->H.n, n3 = 3 * n;
+  if (timed) check_hip(hm::launch_rk_stamp(w.st, 0, s), "stamp launch");
   check_hip(hm::launch_rk_begin(w.st, s), "rk begin launch");
   for (int stage = 0; stage < 6; ++stage) {
     const double* yin = y;
@@ -1036,13 +1124,16 @@ void enqueue_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, double* 
     } else {
       check_hip(hm::launch_rs_slip_rate(n, p->V0, p->V_pl, p->a, y, w.xv, w.Vs, s), "slip-rate launch");
     }
+    if (timed) check_hip(hm::launch_rk_stamp(w.st, 1, s), "stamp launch");
     with_pair(
         A, B, s, [&](hipStream_t q) { check_hip(A->product(false, w.xv, w.ax, 1.0, 0.0, q, A->kernel), "product launch"); },
         [&](hipStream_t q) { check_hip(B->product(false, w.xv, w.bx, 1.0, 0.0, q, B->kernel), "product launch"); });
+    if (timed) check_hip(hm::launch_rk_stamp(w.st, 2, s), "stamp launch");
     check_hip(hm::launch_rs_rhs(n, *p, yin, w.ax, B ? w.bx : nullptr, w.k + stage * n3, s), "rhs launch");
   }
   check_hip(hm::launch_rk_finish_control(n3, w.st, y, w.k, w.y5, s), "error launch");
   check_hip(hm::launch_rk_accept(n, w.st, p->V0, p->a, w.y5, w.Vs, y, D, dt_log, s), "accept launch");
+  if (timed) check_hip(hm::launch_rk_stamp(w.st, 3, s), "stamp launch");
 }
 
 void put_state(const RkWs& w, const rs_rk45_state* st, long long target, int force, hipStream_t s) {
@@ -1088,42 +1179,77 @@ hmat_status rs_rk45_attempt(hmat_t A, hmat_t B, const rs_params* p, double* y, d
   });
 }
 
+namespace {
+
+// rs_rk45_run, and with `timing` its timed form (stamps in every attempt;
+// the totals are read back into *timing).
+void run_rk(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace, rs_rk45_state* st,
+            int64_t n_accept, int64_t max_attempts, double* dt_log, int32_t use_graph, void* stream,
+            rs_rk45_timing* timing) {
+  check_rk_args(A, B, p, y, D, workspace, st);
+  if (n_accept < 0 || max_attempts < 0) hm::fail(HMAT_EINVAL, "counts must be >= 0");
+  if (n_accept == 0) return;
+  DeviceGuard g(A->device);
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const RkWs w = rk_workspace(workspace, A->H.n);
+  const long long target = st->accepted + n_accept;
+  put_state(w, st, target, -1, s);
+  const bool timed = timing != nullptr;
+  const bool graph = use_graph && s != nullptr;
+  GraphCache& cache = timed ? A->rk_timed_cache : A->rk_cache;
+  if (B && B != A) B->ensure_side();  // not during the capture
+  if (graph) {
+    std::vector<const void*> key{p->a, p->b, p->dc, y, D, workspace, dt_log, s};
+    for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
+    push_handle_key(key, A, B);
+    cache.ensure(key, s, [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, dt_log, cs, timed); });
+  }
+  int64_t launched = 0;
+  for (;;) {
+    int64_t batch = target - st->accepted;
+    if (max_attempts > 0) batch = std::min(batch, max_attempts - launched);
+    if (batch <= 0) break;
+    for (int64_t k = 0; k < batch; ++k) {
+      if (graph) check_hip(hipGraphLaunch(cache.exec, s), "hipGraphLaunch");
+      else enqueue_attempt(A, B, p, y, D, w, dt_log, s, timed);
+    }
+    launched += batch;
+    get_state(w, st, s);
+    if (st->accepted >= target) break;
+  }
+  check_wait_flag(A, s);
+  if (B != A) check_wait_flag(B, s);
+  if (timed) {
+    hm::RkDevState d{};
+    check_hip(hipMemcpyAsync(&d, w.st, sizeof(d), hipMemcpyDeviceToHost, s), "hipMemcpyAsync");
+    check_hip(hipStreamSynchronize(s), "hipStreamSynchronize");
+    int rate_khz = 0;
+    check_hip(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, A->device), "hipDeviceGetAttribute");
+    if (rate_khz <= 0) hm::fail(HMAT_EDEVICE, "device reports no wall-clock rate");
+    timing->product_ms = (double)d.prof_prod / rate_khz;
+    timing->attempt_ms = (double)d.prof_att / rate_khz;
+    timing->attempts = launched;
+  }
+  if (st->accepted < target) hm::fail(HMAT_ESTATE, "target not reached within max_attempts");
+}
+
+}  // namespace
+
 hmat_status rs_rk45_run(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
                         rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, double* dt_log, int32_t use_graph,
                         void* stream) {
   return guarded([&] {
-    check_rk_args(A, B, p, y, D, workspace, st);
-    if (n_accept < 0 || max_attempts < 0) hm::fail(HMAT_EINVAL, "counts must be >= 0");
-    if (n_accept == 0) return;
-    DeviceGuard g(A->device);
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    const RkWs w = rk_workspace(workspace, A->H.n);
-    const long long target = st->accepted + n_accept;
-    put_state(w, st, target, -1, s);
-    const bool graph = use_graph && s != nullptr;
-    if (B && B != A) B->ensure_side();  // not during the capture
-    if (graph) {
-      std::vector<const void*> key{p->a, p->b, p->dc, y, D, workspace, dt_log, s};
-      for (double c : {p->V0, p->f0, p->eta_rad, p->V_pl}) push_double(key, c);
-      push_handle_key(key, A, B);
-      A->rk_cache.ensure(key, s, [&](hipStream_t cs) { enqueue_attempt(A, B, p, y, D, w, dt_log, cs); });
-    }
-    int64_t launched = 0;
-    for (;;) {
-      int64_t batch = target - st->accepted;
-      if (max_attempts > 0) batch = std::min(batch, max_attempts - launched);
-      if (batch <= 0) break;
-      for (int64_t k = 0; k < batch; ++k) {
-        if (graph) check_hip(hipGraphLaunch(A->rk_cache.exec, s), "hipGraphLaunch");
-        else enqueue_attempt(A, B, p, y, D, w, dt_log, s);
-      }
-      launched += batch;
-      get_state(w, st, s);
-      if (st->accepted >= target) break;
-    }
-    check_wait_flag(A, s);
-    if (B != A) check_wait_flag(B, s);
-    if (st->accepted < target) hm::fail(HMAT_ESTATE, "target not reached within max_attempts");
+    run_rk(A, B, p, y, D, workspace, st, n_accept, max_attempts, dt_log, use_graph, stream, nullptr);
+  });
+}
+
+hmat_status rs_rk45_run_timed(hmat_t A, hmat_t B, const rs_params* p, double* y, double* D, void* workspace,
+                              rs_rk45_state* st, int64_t n_accept, int64_t max_attempts, double* dt_log,
+                              int32_t use_graph, void* stream, rs_rk45_timing* timing) {
+  return guarded([&] {
+    if (!timing) hm::fail(HMAT_EINVAL, "null timing output");
+    *timing = rs_rk45_timing{};
+    run_rk(A, B, p, y, D, workspace, st, n_accept, max_attempts, dt_log, use_graph, stream, timing);
   });
 }
 

@@ -94,18 +94,31 @@ __global__ void k_stage_slip(int64_t n, int s, const RkDevState* __restrict__ st
   x[i] = V - V_pl;
 }
 
+// Wall-clock stamps of a timed run (one thread): 0 starts an attempt, 1 a
+// product pair, 2 ends the pair (its ticks summed), 3 ends the attempt.
+__global__ void k_stamp(RkDevState* st, int which) {
+  const unsigned long long now = wall_clock64();
+  switch (which) {
+    case 0: st->prof_a0 = now; break;
+    case 1: st->prof_t0 = now; break;
+    case 2: st->prof_prod += now - st->prof_t0; break;
+    default: st->prof_att += now - st->prof_a0; break;
+  }
+}
+
 __global__ void k_begin(RkDevState* st) {
-  if (threadIdx.x < kErrSlots) st->err_bits[threadIdx.x] = 0ull;
+  if (threadIdx.x < kErrSlots) st->err_bits[threadIdx.x * kErrStride] = 0ull;
 }
 
 // y5, and max_i |y5 - y4| / max(|y5|, 1e-300) (non-negative doubles order like
 // their bit patterns, so the maximum is an integer atomic max; NaN wins).
-// Grid-stride over the 3n components with at most kFinishBlocks workgroups;
-// k_1 has weight 0 in both solutions of the pair and is not read.  Each
-// workgroup folds its maximum into one of the kErrSlots slots: the result
-// does not depend on the grid (a maximum is exact in any order).
+// Grid-stride over the 3n components with at most kFinishBlocks workgroups
+// (one component per thread up to n3 = 2^20); k_1 has weight 0 in both
+// solutions of the pair and is not read.  Each workgroup folds its maximum
+// into one of the kErrSlots slots: the result does not depend on the grid
+// (a maximum is exact in any order).
 constexpr int kFinishThreads = 256;
-constexpr int kFinishBlocks = 512;
+constexpr int kFinishBlocks = 4096;
 
 __global__ __launch_bounds__(kFinishThreads) void k_finish(int64_t n3, RkDevState* st, const double* __restrict__ y,
                                                            const double* __restrict__ k, double* __restrict__ y5) {
@@ -143,7 +156,7 @@ __global__ __launch_bounds__(kFinishThreads) void k_finish(int64_t n3, RkDevStat
   if (threadIdx.x == 0) {
     double m = part[0];
     for (int w = 1; w < kFinishThreads / 64; ++w) m = (part[w] != part[w] || part[w] > m) ? part[w] : m;
-    atomicMax(&st->err_bits[blockIdx.x % kErrSlots], (unsigned long long)__double_as_longlong(m));
+    atomicMax(&st->err_bits[(blockIdx.x % kErrSlots) * kErrStride], (unsigned long long)__double_as_longlong(m));
   }
 }
 
@@ -157,7 +170,10 @@ __global__ void k_control(RkDevState* st) {
     return;
   }
   unsigned long long bits = st->err_bits[0];
-  for (int q = 1; q < kErrSlots; ++q) bits = st->err_bits[q] > bits ? st->err_bits[q] : bits;
+  for (int q = 1; q < kErrSlots; ++q) {
+    const unsigned long long v = st->err_bits[q * kErrStride];
+    bits = v > bits ? v : bits;
+  }
   const double err = __longlong_as_double((long long)bits);
   const double r = err / st->eps;
   const double dt = st->dt;
@@ -209,8 +225,13 @@ hipError_t launch_rk_stage_slip(int64_t n, int s, const RkDevState* st, double d
   return hipGetLastError();
 }
 
+hipError_t launch_rk_stamp(RkDevState* st, int which, hipStream_t strm) {
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(1), 0, strm, st, which);
+  return hipGetLastError();
+}
+
 hipError_t launch_rk_begin(RkDevState* st, hipStream_t strm) {
-  hipLaunchKernelGGL(k_begin, dim3(1), dim3(kErrSlots), 0, strm, st);
+  hipLaunchKernelGGL(k_begin, dim3(1), dim3(64), 0, strm, st);
   return hipGetLastError();
 }
 

@@ -24,6 +24,9 @@ hipError_t launch_rs_rhs(int64_t n, const rs_params& p, const double* y, const d
 // All read the step from the device state, so the sequence can be captured
 // in a graph.
 hipError_t launch_rk_begin(RkDevState* st, hipStream_t strm);
+// Wall-clock stamp of a timed run (which: 0 attempt start, 1 product start,
+// 2 product end, 3 attempt end).
+hipError_t launch_rk_stamp(RkDevState* st, int which, hipStream_t strm);
 // Cash-Karp stage input ys = y + dt sum_{j<s} a_sj k_j (k: 6 blocks of 3n,
 // s in 1..5) and x = V(ys) - V_pl (eq. (7)).  dt is read from st, or taken
 // from the argument when st is null (frozen steps).

@@ -215,6 +215,32 @@ def test_autotune_and_profile(torch_dev, hm):
     Hg.close()
 
 
+def test_autotune_choice_is_remembered(torch_dev, hm):
+    """A second handle on the same blocks (same storage, options and
+    device) takes the schedule the first one timed, without timing the
+    candidates again: the same choice in a fraction of the time, and the
+    same products bit for bit."""
+    import time
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case("dip30_150x70")
+    B = oracle_blocks(H)
+    xd = torch.tensor(loguniform_rates(f.n, 10), device=dev)
+    picks, secs, ys = [], [], []
+    for _ in range(2):
+        Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec="f32", kernel="auto",
+                                    unit_kib=128)
+        t0 = time.perf_counter()
+        info = Hg.autotune(reps=5)
+        secs.append(time.perf_counter() - t0)
+        picks.append((info["kernel"], info["wg_waves"], info["wg_waves_p1"]))
+        ys.append(Hg.matvec(xd).cpu().numpy())
+        Hg.close()
+    say(f"[autotune cache] {picks[0]}: first {secs[0]:.3f} s, second {secs[1]:.3f} s")
+    assert picks[1] == picks[0]
+    assert secs[1] <= 0.5 * secs[0]
+    assert np.array_equal(ys[0], ys[1])
+
+
 @pytest.mark.parametrize("wg,wg1", [(8, 4), (4, 4), (8, 8)])
 def test_row_split_layouts(torch_dev, hm, wg, wg1):
     """Small matrices split their oversized phase-1 units by rows, with the

@@ -241,3 +241,28 @@ def test_rk45_with_persistent_products(case):
         sl = slice(c * n, (c + 1) * n)
         assert np.max(np.abs(y2[sl] - y1[sl])) <= 1e-10 * np.max(np.abs(y1[sl]))
     assert np.max(np.abs(D2 - D1)) <= 1e-10 * np.max(np.abs(D1))
+
+
+def test_timed_run_matches_run(case):
+    """rs_rk45_run_timed: the same state, slip and step counts as rs_rk45_run
+    (the stamps change no arithmetic), and a product time within the
+    attempt time."""
+    torch, hm, f, H, p, Hg, dp, dev = case
+    y0 = _state(f, p, 4, kick=0.02)
+    out = []
+    for timed in (False, True):
+        rk = hm.RK45(Hg, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+        y = torch.tensor(y0, device=dev)
+        D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            tm = rk.run_timed(y, D, 25, use_graph=True, stream=s) if timed else rk.run(y, D, 25, use_graph=True,
+                                                                                        stream=s)
+        s.synchronize()
+        out.append((y.cpu().numpy(), D.cpu().numpy(), rk.state.accepted, rk.state.rejected, tm))
+    (y1, D1, a1, r1, _), (y2, D2, a2, r2, tm) = out
+    say(f"[rk45 timed] planar64x32: products {tm['product_ms']:.3f} of {tm['attempt_ms']:.3f} ms, "
+        f"{tm['attempts']} attempts")
+    assert np.array_equal(y1, y2) and np.array_equal(D1, D2) and (a1, r1) == (a2, r2)
+    assert tm["attempts"] == a2 + r2
+    assert 0.0 < tm["product_ms"] < tm["attempt_ms"]
