@@ -128,8 +128,10 @@ typedef struct {
                               rules; blocks beyond rank 64 fall back to the host); 0 = host
                               threads.  Ignored by hmat_build_host. */
   int32_t mm_groups;       /* hmat_matmat: groups of four waves sharing each 64-output slice
-                              (1 or 2) in both phases and modes; 0 = the faster of 1 and 2
-                              per phase and mode, timed at creation (and by hmat_autotune) */
+                              (1 or 2) in both phases and modes; 3 = phase 2 on pairs of row
+                              intervals that stage their common inputs once (phase 1 one
+                              group); 0 = per phase and mode the fastest of these, timed at
+                              creation (and by hmat_autotune) */
 } hmat_opts;
 
 /* Arithmetic of hmat_matmat: FP32 factors and member values are split into
@@ -166,8 +168,9 @@ typedef struct {
   int32_t wg_waves;
   int32_t lattice;
   int32_t wg_waves_p1;
-  int32_t mm_groups;       /* hmat_matmat wave groups, 4 bits each: BF16x3 phase 1, phase 2,
-                              BF16x6 phase 1, phase 2 from the low bits; 0 without max_nrhs */
+  int32_t mm_groups;       /* hmat_matmat schedule, 4 bits each: BF16x3 phase 1, phase 2,
+                              BF16x6 phase 1, phase 2 from the low bits (1 or 2 wave groups, 3
+                              pairs of row intervals); 0 without max_nrhs */
 } hmat_stats;
 
 /* Host copy of the blocks of a handle, in cluster order (hmat_export /

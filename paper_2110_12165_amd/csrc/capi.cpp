@@ -144,6 +144,8 @@ struct hmat_s {
   int32_t max_nout_p1 = 0;
   int32_t* mm_slices1 = nullptr;  // ensemble product: 64-output slices of the phase-1 units
   int32_t mm_ns1 = 0;
+  int32_t* mm_pairs = nullptr;    // ensemble product: pairs of phase-2 units sharing common inputs
+  int32_t mm_npairs = 0;
   // ensemble product: wave groups per 64-output slice, [mode - BF16X3][phase - 1]
   int32_t mm_groups[2][2] = {{1, 1}, {1, 1}};
   double* rs_x = nullptr;  // n doubles: slip rate minus plate rate (rs_rhs scratch)
@@ -217,6 +219,8 @@ struct hmat_s {
     mm_ts = nullptr;
     mm_slices1 = nullptr;
     mm_ns1 = 0;
+    mm_pairs = nullptr;
+    mm_npairs = 0;
   }
 
   template <typename T>
@@ -301,6 +305,8 @@ struct hmat_s {
     a.cus = cus;
     a.groups1 = mm_groups[mode - HMAT_MM_BF16X3][0];
     a.groups2 = mm_groups[mode - HMAT_MM_BF16X3][1];
+    a.pairs = mm_pairs;
+    a.npairs = mm_npairs;
     a.src = batched.src;
     a.pool = batched.pool;
     a.perm = d_perm;
@@ -322,7 +328,8 @@ struct hmat_s {
     // Row-split phase-1 units write partial intermediate values that the
     // ensemble product cannot add (it stages them split into bf16 parts):
     // handles with ensemble buffers keep whole units.
-    hm::BatchedLayout<T> L = hm::make_batched<T>(H, wg, unit_bytes, wg1, false, opts.n_threads, split_slots<T>(wg1));
+    hm::BatchedLayout<T> L =
+        hm::make_batched<T>(H, wg, unit_bytes, wg1, false, opts.n_threads, split_slots<T>(wg1), opts.max_nrhs > 0);
     batched.units = upload(L.units, s, true);
     batched.n1 = L.n1;
     batched.n2 = L.n2;
@@ -348,6 +355,8 @@ struct hmat_s {
         for (int32_t k = 0; 64 * k < L.units[i].nout; ++k) sl.push_back(16 * i + k);
       mm_ns1 = (int32_t)sl.size();
       if (!sl.empty()) mm_slices1 = upload(sl, s, true);
+      mm_npairs = (int32_t)(L.pairs.size() / 2);
+      if (mm_npairs > 0) mm_pairs = upload(L.pairs, s, true);
     }
     grid = hm::persistent_blocks_per_cu<T>(wg) * cus;
     st.n_units_p1 = L.n1;
@@ -407,7 +416,7 @@ void check_opts(const hmat_opts& o, bool build) {
   if (o.max_nrhs < 0) hm::fail(HMAT_EINVAL, "max_nrhs must be >= 0");
   if (o.transpose != 0 && o.transpose != 1) hm::fail(HMAT_EINVAL, "transpose must be 0 or 1");
   if (o.build_device != 0 && o.build_device != 1) hm::fail(HMAT_EINVAL, "build_device must be 0 or 1");
-  if (o.mm_groups < 0 || o.mm_groups > 2) hm::fail(HMAT_EINVAL, "mm_groups must be 0, 1 or 2");
+  if (o.mm_groups < 0 || o.mm_groups > 3) hm::fail(HMAT_EINVAL, "mm_groups must be 0, 1, 2 or 3");
 }
 
 // Default schedule of the batched product (fastest measured on MI355X for
@@ -490,7 +499,10 @@ void tune_store(uint64_t key, int kind, const std::array<int32_t, 4>& v) {
 // temporary buffer.
 void tune_mm(hmat_s* h, hipStream_t s) {
   if (h->opts.mm_groups) {
-    for (auto& m : h->mm_groups) m[0] = m[1] = h->opts.mm_groups;
+    for (auto& m : h->mm_groups) {
+      m[0] = h->opts.mm_groups == hm::kGroupsPairs ? 1 : h->opts.mm_groups;
+      m[1] = h->opts.mm_groups;
+    }
     ++h->gen;
     return;
   }
@@ -522,9 +534,11 @@ void tune_mm(hmat_s* h, hipStream_t s) {
   hipEvent_t ev[3] = {e[0].e, e[1].e, e[2].e};
   for (int m = 0; m < 2; ++m) {
     const int32_t mode = HMAT_MM_BF16X3 + m;
-    double ms[2][2] = {};  // [groups - 1][phase - 1]
-    for (int g = 0; g < 2; ++g) {
-      h->mm_groups[m][0] = h->mm_groups[m][1] = g + 1;
+    double ms[3][2] = {};  // [choice][phase - 1]: one group, two groups, pairs (phase 2 only)
+    const int nchoice = h->mm_npairs > 0 ? 3 : 2;
+    for (int g = 0; g < nchoice; ++g) {
+      h->mm_groups[m][0] = g == 2 ? 1 : g + 1;
+      h->mm_groups[m][1] = g == 2 ? hm::kGroupsPairs : g + 1;
       const hm::MMArgs a = h->mm_args(static_cast<const double*>(bx.p), 64, static_cast<double*>(by.p), 64, 64, mode);
       for (int r = 0; r < 2 + kMMTuneReps; ++r) {
         check_hip(hm::launch_mm(a, mode, 1.0, 0.0, s, ev), "ensemble launch");
@@ -537,7 +551,11 @@ void tune_mm(hmat_s* h, hipStream_t s) {
         ms[g][1] += t2;
       }
     }
-    for (int p = 0; p < 2; ++p) h->mm_groups[m][p] = ms[1][p] < ms[0][p] ? 2 : 1;
+    h->mm_groups[m][0] = ms[1][0] < ms[0][0] ? 2 : 1;
+    int best = 0;
+    for (int g = 1; g < nchoice; ++g)
+      if (ms[g][1] < ms[best][1]) best = g;
+    h->mm_groups[m][1] = best == 2 ? hm::kGroupsPairs : best + 1;
   }
   tune_store(key, kTuneMMGroups, {h->mm_groups[0][0], h->mm_groups[0][1], h->mm_groups[1][0], h->mm_groups[1][1]});
   ++h->gen;

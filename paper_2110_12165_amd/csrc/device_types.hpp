@@ -40,8 +40,12 @@ struct UnitEntry {
 // Waves w < S*RG work: output group w % S (outputs 64*(w % S) + lane), input
 //   groups q = w / S (mod RG); partial sums of the RG input groups are added
 //   in LDS in a fixed order.
+// ncom (kind 2, layouts for the ensemble product): the first ncom inputs are
+//   the ones this interval shares with the other interval of its pair, in
+//   the same order in both lists (0 otherwise).
 struct Unit {
   int32_t nout, nq, S, RG, in0, nin, out0, kind;
+  int32_t ncom, pad;
   int64_t off;
 };
 

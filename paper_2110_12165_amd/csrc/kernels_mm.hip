@@ -336,6 +336,164 @@ __global__ __launch_bounds__(kWaves * 64 * G2) void k_mm(MMArgs a, double alpha,
   }
 }
 
+// Phase 2 on pairs of row intervals (layouts built with paired inputs:
+// Unit::ncom leading inputs are common to both intervals of a pair, in the
+// same order).  Eight waves: group g (four waves) owns interval g of the
+// pair, 16 rows per wave and all 64 members, over its own panel.  Round r
+// (inputs r KS + [0, KS) of a group's list) lies wholly inside the common
+// inputs for r < ncom / KS: those rounds are staged once, by all eight
+// waves, into shared LDS rows that both groups read; every later round each
+// group stages from its own list into its own rows.  A pair stages its
+// common inputs once instead of twice (at N = 122880: 0.53 GB of staging
+// demand instead of 0.88 GB).  Rounds are software-pipelined like k_mm's.
+constexpr int kPairWaves = 2 * kWaves;
+
+template <int NS, int KS>
+__device__ __forceinline__ void pair_stage_load(const MMArgs& a, const int32_t* __restrict__ src, int c0, int K,
+                                                int e0, int estep, s16x8 (&sr)[NS][KS * 8 / (kWaves * 64)]) {
+  const __bf16* __restrict__ Xs = static_cast<const __bf16*>(a.Xs);
+  const __bf16* Ts = static_cast<const __bf16*>(a.Ts);
+  constexpr int kItems = KS * 8 / (kWaves * 64);
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int e = e0 + it * estep;
+    const int ch = e & 7, k = c0 + (e >> 3);
+    const __bf16* row = nullptr;
+    int64_t part = 0;
+    if (e < KS * 8 && k < K) {
+      const int sx = src[k];
+      if (sx >= 0) {
+        row = Xs + (int64_t)a.invperm[sx] * kNR;
+        part = a.n * kNR;
+      } else if (sx < -1) {
+        row = Ts + (int64_t)(-sx - 1) * kNR;
+        part = a.t_size * kNR;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < NS; ++p)
+      sr[p][it] = row ? *reinterpret_cast<const s16x8*>(row + p * part + 8 * ch) : s16x8{0, 0, 0, 0, 0, 0, 0, 0};
+  }
+}
+
+template <int NS, int KS>
+__device__ __forceinline__ void pair_stage_store(unsigned short (*zs)[KS][kNR], int e0, int estep,
+                                                 const s16x8 (&sr)[NS][KS * 8 / (kWaves * 64)]) {
+  constexpr int kItems = KS * 8 / (kWaves * 64);
+#pragma unroll
+  for (int it = 0; it < kItems; ++it) {
+    const int e = e0 + it * estep;
+    if (e >= KS * 8) continue;
+    const int ch = e & 7, kk = e >> 3;
+#pragma unroll
+    for (int p = 0; p < NS; ++p) *reinterpret_cast<s16x8*>(&zs[p][kk][8 * zchunk(kk, ch)]) = sr[p][it];
+  }
+}
+
+template <int NS, int KS>
+__global__ __launch_bounds__(kPairWaves * 64) void k_mm_pair(MMArgs a, double alpha, double beta) {
+  // [0]: shared rows of the common rounds; [1 + g]: rows of group g
+  __shared__ __attribute__((aligned(16))) unsigned short zs[3][NS][KS][kNR];
+  const int ia = a.pairs[2 * blockIdx.x], ib = a.pairs[2 * blockIdx.x + 1];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int grp = wave / kWaves, gw = wave % kWaves, gtid = tid % (kWaves * 64);
+  const int mine = grp == 0 ? ia : ib;  // -1: interval without a partner, group 1 idle
+  Unit u{};
+  if (mine >= 0) u = a.units[a.n1 + mine];
+  const float* pool = static_cast<const float*>(a.pool);
+  const int lm = lane & 15, lk = lane >> 4;
+  const int K = u.nq * 4;
+  const int rounds = (K + KS - 1) / KS;
+  const Unit ua = a.units[a.n1 + ia];
+  const int rounds_a = (ua.nq * 4 + KS - 1) / KS;
+  const int rounds_b = ib >= 0 ? (a.units[a.n1 + ib].nq * 4 + KS - 1) / KS : 0;
+  const int total = max(rounds_a, rounds_b);
+  const int nsh = ib >= 0 ? ua.ncom / KS : 0;  // rounds inside the common inputs
+  const int32_t* src_a = a.src + ua.in0;        // the common inputs, as listed by interval a
+  const int32_t* src_me = a.src + u.in0;
+  const int ntiles = (u.nout + 15) >> 4;
+  const int o = gw * 16 + lm;
+  const bool work = gw < ntiles, orow = work && o < u.nout;
+  f32x4 acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  constexpr int kItems = KS * 8 / (kWaves * 64);
+  s16x8 sr[NS][kItems];
+  f32x4 ar[KS / 32][2], an[KS / 32][2];
+  // staging of round r: shared rounds by all eight waves (items tid, tid + 512,
+  // ...), the others by each group for itself (gtid, gtid + 256, ...)
+  auto load_round = [&](int r) {
+    if (r < nsh) pair_stage_load<NS, KS>(a, src_a, r * KS, ua.nq * 4, tid, kPairWaves * 64, sr);
+    else if (r < rounds) pair_stage_load<NS, KS>(a, src_me, r * KS, K, gtid, kWaves * 64, sr);
+  };
+  auto store_round = [&](int r) {
+    if (r < nsh) pair_stage_store<NS, KS>(zs[0], tid, kPairWaves * 64, sr);
+    else if (r < rounds) pair_stage_store<NS, KS>(zs[1 + grp], gtid, kWaves * 64, sr);
+  };
+  load_round(0);
+  if (work && rounds > 0) load_a(pool, u, 0, o, orow, lk, ar);
+  store_round(0);
+  __syncthreads();
+  for (int r = 0; r < total; ++r) {
+    const bool more = r + 1 < total;
+    if (more) {
+      load_round(r + 1);
+      if (work && r + 1 < rounds) load_a(pool, u, (r + 1) * KS, o, orow, lk, an);
+    }
+    if (work && r < rounds) {
+      const int region = r < nsh ? 0 : 1 + grp;
+#pragma unroll
+      for (int st = 0; st < KS / 32; ++st) {
+        bf16x8 ap[NS];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __bf16 pp[NS];
+          split<NS>(ar[st][j >> 2][j & 3], pp);
+#pragma unroll
+          for (int i = 0; i < NS; ++i) ap[i][j] = pp[i];
+        }
+#pragma unroll
+        for (int nt = 0; nt < 4; ++nt) {
+          bf16x8 bp[NS];
+#pragma unroll
+          for (int i = 0; i < NS; ++i)
+            bp[i] = __builtin_bit_cast(bf16x8, b_fragment(zs[region][i], 32 * st, nt * 16, lane));
+#pragma unroll
+          for (int i = 0; i < NS; ++i)
+#pragma unroll
+            for (int j = 0; j < NS - i; ++j)
+              acc[nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ap[i], bp[j], acc[nt], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    __syncthreads();
+    if (more) {
+      store_round(r + 1);
+#pragma unroll
+      for (int st = 0; st < KS / 32; ++st) {
+        ar[st][0] = an[st][0];
+        ar[st][1] = an[st][1];
+      }
+      __syncthreads();
+    }
+  }
+  if (!work) return;
+#pragma unroll
+  for (int nt = 0; nt < 4; ++nt) {
+    const int r = nt * 16 + lm;
+    if (r >= a.nrhs) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int oo = gw * 16 + 4 * lk + i;
+      if (oo >= u.nout) continue;
+      double* yp = a.Y + (int64_t)a.perm[u.out0 + oo] * a.ldy + r;
+      const float v = acc[nt][i];
+      *yp = beta == 0.0 ? alpha * (double)v : fma(alpha, (double)v, beta * *yp);
+    }
+  }
+}
+
 constexpr int kManySlices = 16;  // phase-1 slices per compute unit from which BF16x6 stages 32 inputs
 
 template <int NS>
@@ -364,7 +522,9 @@ hipError_t launch_ns(const MMArgs& a, double alpha, double beta, hipStream_t s, 
   if (ev) (void)hipEventRecord(ev[1], s);
   if (a.n2 > 0) {
     constexpr int KS2 = NS == 3 ? 32 : 64;
-    if (two2) hipLaunchKernelGGL((k_mm<NS, 2, KS2, 2>), g2, dim3(2 * kWaves * 64), 0, s, a, alpha, beta);
+    if (a.groups2 == kGroupsPairs && a.npairs > 0)
+      hipLaunchKernelGGL((k_mm_pair<NS, KS2>), dim3((unsigned)a.npairs), dim3(kPairWaves * 64), 0, s, a, alpha, beta);
+    else if (two2) hipLaunchKernelGGL((k_mm<NS, 2, KS2, 2>), g2, dim3(2 * kWaves * 64), 0, s, a, alpha, beta);
     else hipLaunchKernelGGL((k_mm<NS, 2, KS2, 1>), g2, dim3(kWaves * 64), 0, s, a, alpha, beta);
   }
   if (ev) (void)hipEventRecord(ev[2], s);

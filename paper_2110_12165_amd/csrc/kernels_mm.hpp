@@ -25,8 +25,15 @@ struct MMArgs {
   int64_t ldy;
   int32_t nrhs;            // 1..64
   int32_t cus;             // compute units of the device
-  int32_t groups1, groups2;  // wave groups (1 or 2) sharing a 64-output slice in phase 1, phase 2
+  int32_t groups1, groups2;  // wave groups (1 or 2) sharing a 64-output slice in phase 1, phase 2;
+                             // groups2 == kGroupsPairs: phase 2 on pairs of row intervals
+  const int32_t* pairs;      // pairs of phase-2 units (a, b; b = -1 alone), or null
+  int32_t npairs;
 };
+
+// Phase-2 schedule value of MMArgs::groups2 (and of the handle's choice)
+// that runs the pairs of row intervals sharing their common inputs.
+constexpr int32_t kGroupsPairs = 3;
 
 // parts = 2 (3 bf16 products, "BF16x3") or 3 (6 products, "BF16x6").
 // ev (optional): 3 events, before / between the phases / after.

@@ -196,7 +196,7 @@ PlainLayout<T> make_plain(const HostMatrix& H, bool transpose, int32_t n_threads
 
 template <typename T>
 BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1,
-                              bool transpose, int32_t n_threads, int64_t split_slots) {
+                              bool transpose, int32_t n_threads, int64_t split_slots, bool pair_inputs) {
   constexpr int W = 16 / (int)sizeof(T);
   BatchedLayout<T> L;
   L.wg_waves = wg_waves;
@@ -311,7 +311,7 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
         const int64_t r0 = (int64_t)p * g.nq_part * W;
         const int64_t rows = std::min(g.n - r0, g.nq_part * W);
         if (rows <= 0) continue;
-        Unit u;
+        Unit u{};
         u.kind = 1;
         u.nout = (int32_t)ns;
         u.nq = to_i32((rows + W - 1) / W, "unit inputs");
@@ -326,33 +326,74 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
     }
   }
   // ---- phase 2: one unit per refined row interval --------------------------
+  // Inputs of an interval: the columns of every dense block meeting it, then
+  // the rank columns of every low-rank block meeting it (Col: block, column
+  // or rank index, the interval's first row inside the block, source).
+  struct Col {
+    int32_t b, j, i0, src;
+  };
   Incidence I = incidence(H, transpose, 64);
+  std::vector<std::vector<Col>> cols(I.iv.size());
+  for (size_t k = 0; k < I.iv.size(); ++k)
+    for (int pass = 0; pass < 2; ++pass)
+      for (auto& e : I.members[k]) {
+        const int64_t b = e.first;
+        if (pass == 0 && B.kind(b) == 0) {
+          for (int64_t j = 0; j < B.n(b); ++j)
+            cols[k].push_back({(int32_t)b, (int32_t)j, e.second, H.perm[B.c0(b) + j]});
+        } else if (pass == 1 && B.kind(b) == 1 && B.rank(b) > 0) {
+          for (int64_t kk = 0; kk < B.rank(b); ++kk) {
+            const int64_t slot = slot_of_block[b] + kk;
+            const int64_t j = sum_of_slot[slot];
+            cols[k].push_back({(int32_t)b, (int32_t)kk, e.second,
+                               j < 0 ? -(int32_t)slot - 1 : -(int32_t)(L.t_size + j) - 1});
+          }
+        }
+      }
+  // pairs of consecutive intervals: the inputs both use first, in the order
+  // of the first interval's list, then each interval's own
+  std::vector<int32_t> ncom(I.iv.size(), 0);
+  if (pair_inputs) {
+    parallel_for((int64_t)I.iv.size() / 2, n_threads, [&](int64_t pj) {
+      std::vector<Col>& a = cols[2 * pj];
+      std::vector<Col>& b = cols[2 * pj + 1];
+      std::map<int32_t, size_t> in_b;
+      for (size_t i = 0; i < b.size(); ++i) in_b.emplace(b[i].src, i);
+      std::vector<Col> na, nb, ra;
+      std::vector<char> taken(b.size(), 0);
+      for (const Col& c : a) {
+        auto it = in_b.find(c.src);
+        if (it == in_b.end()) {
+          ra.push_back(c);
+        } else {
+          na.push_back(c);
+          nb.push_back(b[it->second]);
+          taken[it->second] = 1;
+        }
+      }
+      ncom[2 * pj] = ncom[2 * pj + 1] = (int32_t)na.size();
+      na.insert(na.end(), ra.begin(), ra.end());
+      for (size_t i = 0; i < b.size(); ++i)
+        if (!taken[i]) nb.push_back(b[i]);
+      a.swap(na);
+      b.swap(nb);
+    });
+  }
   for (size_t k = 0; k < I.iv.size(); ++k) {
     const int64_t a = I.iv[k].first, m = I.iv[k].second - I.iv[k].first;
-    Unit u;
+    Unit u{};
     u.kind = 2;
     u.nout = (int32_t)m;
     u.S = 1;
     u.RG = wg_waves;
     u.in0 = to_i32((int64_t)L.src.size(), "input list");
     u.out0 = (int32_t)a;
+    u.ncom = ncom[k];
     int64_t K = 0;
-    // dense columns first, then low-rank columns
-    for (int pass = 0; pass < 2; ++pass)
-      for (auto& e : I.members[k]) {
-        const int64_t b = e.first;
-        if (pass == 0 && B.kind(b) == 0) {
-          for (int64_t j = 0; j < B.n(b); ++j) L.src.push_back(H.perm[B.c0(b) + j]);
-          K += B.n(b);
-        } else if (pass == 1 && B.kind(b) == 1 && B.rank(b) > 0) {
-          for (int64_t kk = 0; kk < B.rank(b); ++kk) {
-            const int64_t slot = slot_of_block[b] + kk;
-            const int64_t j = sum_of_slot[slot];
-            L.src.push_back(j < 0 ? -(int32_t)slot - 1 : -(int32_t)(L.t_size + j) - 1);
-          }
-          K += B.rank(b);
-        }
-      }
+    for (const Col& c : cols[k]) {
+      L.src.push_back(c.src);
+      ++K;
+    }
     while (K % W) {
       L.src.push_back(-1);
       ++K;
@@ -410,25 +451,39 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
         for (int64_t o = 0; o < m; ++o) dst[(q * m + o) * W + c] = colv ? (T)colv[o * stride] : T(0);
         ++col;
       };
-      for (int pass = 0; pass < 2; ++pass)
-        for (auto& e : I.members[p.g]) {
-          const int64_t b = e.first, i0 = e.second;
-          if (pass == 0 && B.kind(b) == 0) {
-            for (int64_t j = 0; j < B.n(b); ++j) {
-              const auto cs = B.dense_col(b, j);
-              put(cs.first + i0 * cs.second, cs.second);
-            }
-          } else if (pass == 1 && B.kind(b) == 1 && B.rank(b) > 0) {
-            for (int64_t kk = 0; kk < B.rank(b); ++kk) put(B.u_col(b, kk) + i0, 1);
-          }
+      for (const Col& c : cols[p.g]) {
+        if (B.kind(c.b) == 0) {
+          const auto cs = B.dense_col(c.b, c.j);
+          put(cs.first + (int64_t)c.i0 * cs.second, cs.second);
+        } else {
+          put(B.u_col(c.b, c.j) + c.i0, 1);
         }
+      }
       while (col % W) put(nullptr, 0);
     }
   });
   std::vector<Unit> p1, p2;
-  for (auto& p : pend) (p.kind == 1 ? p1 : p2).push_back(p.u);
+  std::vector<int32_t> unit_of_interval(I.iv.size(), -1);
+  for (auto& p : pend) {
+    if (p.kind == 2) unit_of_interval[p.g] = (int32_t)p2.size();
+    (p.kind == 1 ? p1 : p2).push_back(p.u);
+  }
   L.n1 = (int32_t)p1.size();
   L.n2 = (int32_t)p2.size();
+  if (pair_inputs) {
+    std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> pr;
+    for (size_t k = 0; k < I.iv.size(); k += 2) {
+      const int32_t ua = unit_of_interval[k];
+      const int32_t ub = k + 1 < I.iv.size() ? unit_of_interval[k + 1] : -1;
+      const int64_t sz = (int64_t)p2[ua].nq * p2[ua].nout + (ub >= 0 ? (int64_t)p2[ub].nq * p2[ub].nout : 0);
+      pr.push_back({sz, {ua, ub}});
+    }
+    std::stable_sort(pr.begin(), pr.end(), [](const auto& x, const auto& y) { return x.first > y.first; });
+    for (const auto& e : pr) {
+      L.pairs.push_back(e.second.first);
+      L.pairs.push_back(e.second.second);
+    }
+  }
   L.units = std::move(p1);
   L.units.insert(L.units.end(), p2.begin(), p2.end());
   return L;
@@ -437,8 +492,8 @@ BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t uni
 template PlainLayout<float> make_plain<float>(const HostMatrix&, bool, int32_t);
 template PlainLayout<double> make_plain<double>(const HostMatrix&, bool, int32_t);
 template BatchedLayout<float> make_batched<float>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t,
-                                                  int64_t);
+                                                  int64_t, bool);
 template BatchedLayout<double> make_batched<double>(const HostMatrix&, int32_t, int64_t, int32_t, bool, int32_t,
-                                                    int64_t);
+                                                    int64_t, bool);
 
 }  // namespace hm

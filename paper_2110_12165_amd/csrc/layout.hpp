@@ -38,6 +38,10 @@ struct BatchedLayout {
   // (4 slots, unused ones 0) lists the partials of one value, which phase 2
   // adds in that order when a source reads -(t_size + j) - 1.
   std::vector<int32_t> sums;
+  // pair_inputs: phase-2 units in pairs of consecutive row intervals, (a, b)
+  // indices relative to the first phase-2 unit (b = -1 for an interval
+  // without a partner), largest pairs first
+  std::vector<int32_t> pairs;
   int32_t wg_waves = 8;                // waves per workgroup of phase-2 units
   int32_t wg_waves_p1 = 8;             // waves per workgroup of phase-1 units
   int64_t unit_bytes = 0;
@@ -52,9 +56,14 @@ struct BatchedLayout {
 // matrices, where the largest units run alone at the end of the phase),
 // units more than twice the mean are split by rows into up to 4 units with
 // partial intermediate values (see sums).  0: no splitting.
+// pair_inputs: consecutive row intervals 2j, 2j + 1 form pairs; the inputs the
+// two share (the same x element or intermediate value) lead both input
+// lists in the same order (Unit::ncom), so that the ensemble product can
+// stage them once for the pair (pairs).
 template <typename T>
 BatchedLayout<T> make_batched(const HostMatrix& H, int32_t wg_waves, int64_t unit_bytes, int32_t wg_waves_p1,
-                              bool transpose = false, int32_t n_threads = 0, int64_t split_slots = 0);
+                              bool transpose = false, int32_t n_threads = 0, int64_t split_slots = 0,
+                              bool pair_inputs = false);
 
 // The blocks of H^T (dense blocks transposed, U and V exchanged), same
 // permutation: packing them gives the layouts of the transpose product.

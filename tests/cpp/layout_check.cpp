@@ -25,13 +25,42 @@ static void die(const char* m, long a = 0, long b = 0) {
   std::exit(1);
 }
 
+// Pairs of a layout built with paired inputs: every phase-2 unit in exactly
+// one pair, partners covering adjacent row intervals, equal common counts
+// and identical leading sources.
+template <typename T>
+static void check_pairs(const BatchedLayout<T>& L) {
+  std::vector<int> seen(L.n2, 0);
+  if (L.pairs.size() % 2) die("pairs list of odd length");
+  for (size_t i = 0; i < L.pairs.size(); i += 2) {
+    const int32_t a = L.pairs[i], b = L.pairs[i + 1];
+    if (a < 0 || a >= L.n2 || b < -1 || b >= L.n2) die("pair index", a, b);
+    if (seen[a]++ || (b >= 0 && seen[b]++)) die("unit in two pairs", a, b);
+    const Unit& ua = L.units[L.n1 + a];
+    if (b < 0) {
+      if (ua.ncom != 0) die("lone interval with common inputs", a, ua.ncom);
+      continue;
+    }
+    const Unit& ub = L.units[L.n1 + b];
+    if (ua.out0 + ua.nout != ub.out0) die("pair not adjacent", ua.out0, ub.out0);
+    if (ua.ncom != ub.ncom || ua.ncom > ua.nin || ub.ncom > ub.nin) die("common count", ua.ncom, ub.ncom);
+    for (int k = 0; k < ua.ncom; ++k)
+      if (L.src[ua.in0 + k] != L.src[ub.in0 + k] || L.src[ua.in0 + k] == -1) die("common source differs", a, k);
+  }
+  for (int32_t k = 0; k < L.n2; ++k)
+    if (!seen[k]) die("unit in no pair", k);
+}
+
 template <typename T>
 static double replay(const HostMatrix& H, int NW, int NW1, int64_t unit_bytes, const std::vector<double>& x,
-                     const std::vector<double>& yref, int64_t split_slots = 0, int64_t* n_sums = nullptr) {
+                     const std::vector<double>& yref, int64_t split_slots = 0, int64_t* n_sums = nullptr,
+                     bool pairs = false) {
   constexpr int W = 16 / (int)sizeof(T);
   constexpr int kStage = 2048;
-  BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes, NW1, false, 0, split_slots);
+  BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes, NW1, false, 0, split_slots, pairs);
   if (n_sums) *n_sums = (int64_t)L.sums.size() / 4;
+  if (pairs) check_pairs(L);
+  else if (!L.pairs.empty()) die("pairs without paired inputs");
   if (L.sums.size() % 4) die("sums not in groups of 4", (long)L.sums.size());
   // every partial slot belongs to exactly one sum; the main slot comes first
   std::vector<int> in_sum(L.t_size, 0);
@@ -248,6 +277,13 @@ int main(int argc, char** argv) {
     const double r32 = replay<float>(H, 8, NW1, 256 << 10, x, yref, 1 << 20, &ns32);
     std::printf("split NW1=%d sums %ld/%ld rel64=%.3e rel32=%.3e\n", NW1, (long)ns64, (long)ns32, r64, r32);
     if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed split product differs");
+  }
+  // inputs ordered in pairs of intervals (layouts of handles with ensemble buffers)
+  for (int NW : {4, 8}) {
+    const double r64 = replay<double>(H, NW, 4, 256 << 10, x, yref, 0, nullptr, true);
+    const double r32 = replay<float>(H, NW, 4, 256 << 10, x, yref, 0, nullptr, true);
+    std::printf("pairs NW=%d rel64=%.3e rel32=%.3e\n", NW, r64, r32);
+    if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed product with paired inputs differs");
   }
   std::printf("OK\n");
   return 0;

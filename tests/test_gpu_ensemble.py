@@ -27,9 +27,11 @@ pytestmark = pytest.mark.gpu
 _oracles = {}
 
 
-# (workload, wave groups per slice: 0 = timed choice, 1 or 2 forced)
+# (workload, schedule: 0 = timed choice, 1 or 2 wave groups per slice forced,
+# 3 phase 2 on pairs of row intervals sharing their common inputs)
 @pytest.fixture(scope="module", params=[("dip30_150x70", 0), ("dip30_150x70", 1), ("dip30_150x70", 2),
-                                        ("planar64x32", 1), ("planar64x32", 2)],
+                                        ("dip30_150x70", 3), ("planar64x32", 1), ("planar64x32", 2),
+                                        ("planar64x32", 3)],
                 ids=lambda p: f"{p[0]}-g{p[1]}")
 def case(request):
     import torch
@@ -48,9 +50,10 @@ def case(request):
     mg = Hg.info()["mm_groups"]
     say(f"[ensemble] {name} wave groups {mg}")
     if groups:
-        assert mg == {"x3": (groups, groups), "x6": (groups, groups)}
+        want = (1, 3) if groups == 3 else (groups, groups)
+        assert mg == {"x3": want, "x6": want}
     else:
-        assert all(v in (1, 2) for m in mg.values() for v in m)
+        assert all(m[0] in (1, 2) and m[1] in (1, 2, 3) for m in mg.values())
     yield torch, hm, f"{name}-g{groups}", f, H, Hg
     Hg.close()
 
@@ -96,7 +99,7 @@ def test_ensemble_matches_single_vector_products(case):
     assert rel(Ym, Yv) <= 2e-5
 
 
-@pytest.mark.parametrize("groups", [0, 1, 2])
+@pytest.mark.parametrize("groups", [0, 1, 2, 3])
 def test_ensemble_degenerate_sizes(groups):
     """Tiny meshes (one element, no low-rank block, a single leaf) and a
     matrix of zeros (the normal component of a planar fault): the ensemble
@@ -147,7 +150,7 @@ def test_autotune_keeps_the_ensemble_product():
     say(f"[ensemble] autotune picked {info['kernel']} {info['wg_waves']}/{info['wg_waves_p1']}, "
         f"wave groups {info['mm_groups']}")
     assert info["kernel"] in ("split", "persistent")
-    assert all(v in (1, 2) for m in info["mm_groups"].values() for v in m)
+    assert all(m[0] in (1, 2) and m[1] in (1, 2, 3) for m in info["mm_groups"].values())
     dev = torch.device("cuda:0")
     X = torch.tensor(loguniform_rates(f.n, 6, nrhs=16), device=dev)
     Ym = Hg.matmat(X, mode="x6").cpu().numpy()

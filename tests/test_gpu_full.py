@@ -75,10 +75,11 @@ def test_full_size_against_exact_product(setup, variant):
     assert info["max_rank"] <= 64 and info["n_lr"] > 40000
 
 
-@pytest.mark.parametrize("groups", [1, 2])
+@pytest.mark.parametrize("groups", [1, 2, 3])
 def test_full_size_ensemble_against_exact_product(setup, groups):
     """The ensemble product (BF16x6 and BF16x3 on MFMA) with one and with
-    two wave groups per 64-output slice, against exact products."""
+    two wave groups per 64-output slice, and with phase 2 on pairs of row
+    intervals, against exact products."""
     torch, hm, bench_options, w, f, x, y_exact = setup
     opts = dict(bench_options(NAME, "batched_f32"), max_nrhs=64, mm_groups=groups)
     H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, **opts)
@@ -92,7 +93,8 @@ def test_full_size_ensemble_against_exact_product(setup, groups):
     H.close()
     r6, r3 = rel(Y6, ref), rel(Y3, ref)
     say(f"[full] {NAME} ensemble groups {groups}: rel x6 {r6:.3e} x3 {r3:.3e}")
-    assert info["mm_groups"] == {"x3": (groups, groups), "x6": (groups, groups)}
+    want = (1, 3) if groups == 3 else (groups, groups)
+    assert info["mm_groups"] == {"x3": want, "x6": want}
     # BF16x3 keeps 16 significant bits of each operand (two bf16 parts) and
     # of each stored intermediate value: about 2^-16 = 1.5e-5 per term,
     # averaging down over a sum; 5e-5 bounds it with room (measured 4.5e-6)

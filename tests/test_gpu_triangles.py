@@ -223,7 +223,7 @@ def test_paper_scale_ensemble_product(component):
     exact = _ORACLE_ROWS[key][component] @ X
     assert np.max(np.abs(ref[rows] - exact)) <= 1e-5 * np.max(np.abs(ref))
     Xd = torch.tensor(X, device=dev)
-    for groups in (1, 2):
+    for groups in (1, 2, 3):
         H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, component=component, aca_eps=w["aca_eps"], eta=w["eta"],
                              leaf=w["leaf"], lattice=w["lattice"], prec="f32", kernel="split", build_device=1,
                              max_nrhs=64, mm_groups=groups)

@@ -108,7 +108,7 @@ def test_invalid_arguments_rejected(lib):
     f = planar_rect_fault(8, 8, 100.0, 90.0, "strike")
     w = dict(aca_eps=1e-6, eta=2.0, leaf=4, lattice=1)
     for bad in (dict(aca_eps=0.0), dict(eta=-1.0), dict(leaf=0), dict(lattice=3), dict(prec=7), dict(kernel=9),
-                dict(wg_waves=5), dict(wg_waves_p1=2), dict(mm_groups=3), dict(mm_groups=-1), dict(transpose=2),
+                dict(wg_waves=5), dict(wg_waves_p1=2), dict(mm_groups=4), dict(mm_groups=-1), dict(transpose=2),
                 dict(build_device=2), dict(max_nrhs=-1), dict(n_threads=-1)):
         st, h = _host_build(lib, f, dict(w, **{k: v for k, v in bad.items() if k in w}),
                             **{k: v for k, v in bad.items() if k not in w})
