@@ -819,6 +819,24 @@ def main():
             ms_t = e0.elapsed_time(e1) / args.steps
             results[variant]["transpose"] = dict(ms=ms_t, matvec_per_s=1e3 / ms_t,
                                                  product_gbs=info["alg_bytes"] / (ms_t * 1e-3) / 1e9)
+            # four vectors per call: the split schedule reads each stored entry once for all four
+            xs = x.repeat(4)
+            ys = torch.empty_like(xs)
+            stream_ptr = torch.cuda.current_stream().cuda_stream
+            for _ in range(args.warmup):
+                H.matvec_raw(xs.data_ptr(), ys.data_ptr(), nrhs=4, ld=f.n, stream_ptr=stream_ptr)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(args.steps):
+                H.matvec_raw(xs.data_ptr(), ys.data_ptr(), nrhs=4, ld=f.n, stream_ptr=stream_ptr)
+            e1.record()
+            torch.cuda.synchronize()
+            ms_4 = e0.elapsed_time(e1) / args.steps
+            dev4 = float((ys.view(4, f.n) - ys.view(4, f.n)[0]).abs().max() / ys.view(4, f.n)[0].abs().max())
+            results[variant]["multi_rhs"] = dict(nrhs=4, ms=ms_4, vectors_per_s=4e3 / ms_4,
+                                                 speedup_vs_single=4 * ms / ms_4, columns_max_rel_diff=dev4)
+            log(f"[bench] {variant}: 4 vectors per call {ms_4 * 1e3:.1f} us ({4e3 / ms_4:.0f} vectors/s, "
+                f"{4 * ms / ms_4:.2f}x four single products)")
             log(f"[bench] {variant}: transposed product {ms_t * 1e3:.1f} us "
                 f"({info['alg_bytes'] / (ms_t * 1e-3) / 1e9:.0f} GB/s)")
         log(f"[bench] {variant}: {1e3 / ms:.1f} matvec/s ({ms * 1e3:.1f} us/product, {whole:.0f} GB/s = "
@@ -872,8 +890,9 @@ def main():
         line[v] = {k: r[k] for k in ("matvec_per_s", "ms", "product_gbs", "product_hbm_frac", "achieved_gbs",
                                      "hbm_frac", "build_s")}
         line[v]["kernel"] = r["info"]["kernel"]
-        if "transpose" in r:
-            line[v]["transpose"] = r["transpose"]
+        for extra in ("transpose", "multi_rhs"):
+            if extra in r:
+                line[v][extra] = r[extra]
     if "plain_f64" in results:
         line["speedup_batched_f32_vs_plain_f64"] = head["matvec_per_s"] / results["plain_f64"]["matvec_per_s"]
     if "batched_f64" in outputs:

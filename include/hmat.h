@@ -241,6 +241,11 @@ hmat_status hmat_export(hmat_t h, hmat_host_blocks* out);
  *   x, y: DEVICE FP64, caller's element order, column-major n x nrhs with
  *     leading dimension ld >= n; x and y must not overlap.
  *   nrhs >= 0 (0 is a no-op); beta == 0 ignores the old contents of y.
+ *   With the split schedule the columns go in passes of 4 (then 2) vectors
+ *   that read each stored entry once per pass; the remaining columns, and
+ *   other schedules, one at a time.  The sums of a row are taken in the same
+ *   order either way up to the length of the staging rounds: results agree
+ *   with single-vector products to rounding.
  *   Allocates nothing and does not wait for the GPU.
  */
 hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int64_t ld,

@@ -253,6 +253,7 @@ struct hmat_s {
     batched_t.n2 = L.n2;
     batched_t.src = upload(L.src, s);
     batched_t.t = alloc_zero<double>((size_t)L.t_size, s);
+    batched_t.tm = alloc_zero<double>((size_t)hm::kMultiMax * L.t_size, s);
     batched_t.sums = L.sums.empty() ? nullptr : upload(L.sums, s);
     batched_t.t_size = (int32_t)L.t_size;
     batched_t.pool = upload(L.pool, s);
@@ -335,6 +336,7 @@ struct hmat_s {
     batched.n2 = L.n2;
     batched.src = upload(L.src, s, true);
     batched.t = alloc_zero<double>((size_t)L.t_size, s, true);
+    batched.tm = alloc_zero<double>((size_t)hm::kMultiMax * L.t_size, s, true);
     batched.sums = L.sums.empty() ? nullptr : upload(L.sums, s, true);
     batched.t_size = (int32_t)L.t_size;
     batched.pool = upload(L.pool, s, true);
@@ -375,6 +377,31 @@ struct hmat_s {
     if (kernel == HMAT_KERNEL_BATCHED_PERSISTENT || wg1 == 0) wg1 = wg;
     if (f32()) setup_batched<float>(wg, unit_bytes, wg1, s);
     else setup_batched<double>(wg, unit_bytes, wg1, s);
+  }
+
+  // nrhs vectors (column-major, leading dimension ld): with the split
+  // schedule, passes of kMultiMax and then 2 vectors read each panel entry
+  // once per pass; the rest (and the other schedules) one vector at a time.
+  hipError_t products(bool transpose, const double* x, double* y, int64_t nrhs, int64_t ld, double alpha,
+                      double beta, hipStream_t s, int32_t kern) const {
+    int64_t c = 0;
+    const bool multi = kern == HMAT_KERNEL_BATCHED_SPLIT && (!transpose || has_batched_t);
+    if (multi) {
+      const hm::BatchedArgs& a = transpose ? batched_t : batched;
+      for (int nv : {hm::kMultiMax, 2})
+        for (; c + nv <= nrhs; c += nv) {
+          const hipError_t e = f32() ? hm::launch_batched_multi<float>(a, nv, x + c * ld, ld, y + c * ld, ld, alpha,
+                                                                       beta, s)
+                                     : hm::launch_batched_multi<double>(a, nv, x + c * ld, ld, y + c * ld, ld, alpha,
+                                                                        beta, s);
+          if (e != hipSuccess) return e;
+        }
+    }
+    for (; c < nrhs; ++c) {
+      const hipError_t e = product(transpose, x + c * ld, y + c * ld, alpha, beta, s, kern);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
   }
 
   // transpose: H^T, through its batched layout when built, else the natural
@@ -841,8 +868,7 @@ hmat_status hmat_matvec(hmat_t h, const double* x, double* y, int64_t nrhs, int6
     if (nrhs == 0) return;
     DeviceGuard g(h->device);
     const hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int64_t c = 0; c < nrhs; ++c)
-      check_hip(h->product(false, x + c * ld, y + c * ld, alpha, beta, s, h->kernel), "product launch");
+    check_hip(h->products(false, x, y, nrhs, ld, alpha, beta, s, h->kernel), "product launch");
   });
 }
 
@@ -856,8 +882,7 @@ hmat_status hmat_matvec_T(hmat_t h, const double* x, double* y, int64_t nrhs, in
     if (!h->has_batched_t && !(h->has_plain && h->plain.n_cols > 0))
       hm::fail(HMAT_ESTATE, "handle created without opts.transpose");
     const int32_t kt = h->kernel == HMAT_KERNEL_PLAIN ? HMAT_KERNEL_PLAIN : h->kernel;
-    for (int64_t c = 0; c < nrhs; ++c)
-      check_hip(h->product(true, x + c * ld, y + c * ld, alpha, beta, s, kt), "transpose launch");
+    check_hip(h->products(true, x, y, nrhs, ld, alpha, beta, s, kt), "transpose launch");
   });
 }
 

@@ -150,6 +150,135 @@ __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ po
   __syncthreads();
 }
 
+// run_unit for R vectors at once (R = 2 or 4; split schedule): every panel
+// entry is read once and applied to the R vectors' inputs, which are staged
+// in LDS rows of kStage / R entries (vector r at zs[r * kStage / R]).  Vector
+// r reads x + r ldx, writes y + r ldy, and its intermediate values are
+// t + r ldt.  The sums of a row are taken in the same order as run_unit's
+// except for the shorter staging rounds.
+template <typename T, int NW, int R>
+__device__ __forceinline__ void run_unit_multi(const Unit& u, const T* __restrict__ pool, const double* __restrict__ x,
+                                               int64_t ldx, double* __restrict__ y, int64_t ldy,
+                                               const int32_t* __restrict__ perm, const int32_t* __restrict__ src,
+                                               double* t, int64_t ldt, const int32_t* __restrict__ sums, int t_size,
+                                               double alpha, double beta, double* zs, double* red) {
+  using V = typename Pack<T>::vec;
+  constexpr int W = Pack<T>::W;
+  constexpr int U = 8;
+  constexpr int KSR = kStage / R;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int S = u.S, RG = u.RG;
+  const bool working = wave < S * RG;
+  const int sg = wave % S, rg = wave / S;
+  const int o = sg * 64 + lane;
+  const bool active = working && o < u.nout;
+  const int nin_pad = u.nq * W;
+  const size_t stride = (size_t)u.nout;
+  const V* base = reinterpret_cast<const V*>(pool + u.off) + o;
+  double acc[R][4];
+#pragma unroll
+  for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
+
+  for (int c0 = 0; c0 < nin_pad; c0 += KSR) {
+    const int cl = min(KSR, nin_pad - c0);
+    for (int i = tid; i < cl; i += NW * 64) {
+      const int gi = c0 + i;
+      int sx = -1;  // t[0] is the zero pad
+      const int* e = nullptr;
+      if (u.kind == 1) {
+        if (gi < u.nin) sx = perm[u.in0 + gi];
+      } else {
+        const int s = src[u.in0 + gi];
+        if (s >= 0) sx = s;
+        else if (-s - 1 >= t_size) e = sums + 4 * (-s - 1 - t_size);
+        else sx = s;  // negative: -sx - 1 indexes t
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double v;
+        if (e) v = ((t[r * ldt + e[0]] + t[r * ldt + e[1]]) + t[r * ldt + e[2]]) + t[r * ldt + e[3]];
+        else if (sx >= 0) v = x[r * ldx + sx];
+        else v = t[r * ldt + (-sx - 1)];
+        if (u.kind == 1 && gi >= u.nin) v = 0.0;
+        zs[r * KSR + i] = v;
+      }
+    }
+    __syncthreads();
+    if (active) {
+      const int q0 = c0 / W;
+      const int q1 = q0 + cl / W;
+      int q = q0 + rg;
+      for (; q + (U - 1) * RG < q1; q += U * RG) {
+        V v[U];
+#pragma unroll
+        for (int k = 0; k < U; ++k) v[k] = load_stream<T>(base + (size_t)(q + k * RG) * stride);
+#pragma unroll
+        for (int k = 0; k < U; ++k) {
+          const double* z = zs + (q + k * RG - q0) * W;
+#pragma unroll
+          for (int c = 0; c < W; ++c) {
+            const double a = (double)v[k][c];
+#pragma unroll
+            for (int r = 0; r < R; ++r) acc[r][k & 3] = fma(a, z[r * KSR + c], acc[r][k & 3]);
+          }
+        }
+      }
+      for (; q < q1; q += RG) {
+        const V v0 = load_stream<T>(base + (size_t)q * stride);
+        const double* z = zs + (q - q0) * W;
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          const double a = (double)v0[c];
+#pragma unroll
+          for (int r = 0; r < R; ++r) acc[r][0] = fma(a, z[r * KSR + c], acc[r][0]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  double sum[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) sum[r] = (acc[r][0] + acc[r][1]) + (acc[r][2] + acc[r][3]);
+  if (RG > 1) {
+    if (working)
+#pragma unroll
+      for (int r = 0; r < R; ++r) red[(r * NW + wave) * 64 + lane] = sum[r];
+    __syncthreads();
+    if (rg == 0)
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        sum[r] = 0.0;
+        for (int g = 0; g < RG; ++g) sum[r] += red[(r * NW + g * S + sg) * 64 + lane];
+      }
+  }
+  if (rg == 0 && active) {
+    if (u.kind == 1) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) t[r * ldt + u.out0 + o] = sum[r];
+    } else {
+      const int row = perm[u.out0 + o];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double* yp = y + r * ldy + row;
+        *yp = beta == 0.0 ? alpha * sum[r] : fma(alpha, sum[r], beta * *yp);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int NW, int PHASE, int R>
+__global__ __launch_bounds__(NW * 64) void k_phase_multi(BatchedArgs a, const double* __restrict__ x, int64_t ldx,
+                                                         double* __restrict__ y, int64_t ldy, double alpha,
+                                                         double beta) {
+  __shared__ double zs[kStage];
+  __shared__ double red[R * NW * 64];
+  const Unit u = a.units[(PHASE == 1 ? 0 : a.n1) + blockIdx.x];
+  run_unit_multi<T, NW, R>(u, static_cast<const T*>(a.pool), x, ldx, y, ldy, a.perm, a.src, a.tm, a.t_size, a.sums,
+                           a.t_size, alpha, beta, zs, red);
+}
+
 // Split schedule: one launch per phase (distinct symbols), one workgroup per
 // unit, units in decreasing size.
 template <typename T, int NW, int PHASE>
@@ -364,6 +493,24 @@ void launch_persistent(const BatchedArgs& a, int nw, int grid, const double* x, 
   }
 }
 
+template <typename T, int PHASE, int R>
+void launch_phase_multi(const BatchedArgs& a, int nw, unsigned grid, const double* x, int64_t ldx, double* y,
+                        int64_t ldy, double alpha, double beta, hipStream_t s) {
+  switch (nw) {
+    case 4:
+      hipLaunchKernelGGL((k_phase_multi<T, 4, PHASE, R>), dim3(grid), dim3(4 * 64), 0, s, a, x, ldx, y, ldy, alpha,
+                         beta);
+      break;
+    case 8:
+      hipLaunchKernelGGL((k_phase_multi<T, 8, PHASE, R>), dim3(grid), dim3(8 * 64), 0, s, a, x, ldx, y, ldy, alpha,
+                         beta);
+      break;
+    default:
+      hipLaunchKernelGGL((k_phase_multi<T, 16, PHASE, R>), dim3(grid), dim3(16 * 64), 0, s, a, x, ldx, y, ldy, alpha,
+                         beta);
+  }
+}
+
 template <typename T, int NW>
 int occupancy_nw() {
   int nb = 0;
@@ -390,6 +537,21 @@ hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const
   if (ev) (void)hipEventRecord(ev[1], s);
   if (a.n2 > 0) launch_phase<T, 2>(a, a.wg_waves, (unsigned)a.n2, x, y, alpha, beta, s);
   if (ev) (void)hipEventRecord(ev[2], s);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batched_multi(const BatchedArgs& a, int nvec, const double* x, int64_t ldx, double* y, int64_t ldy,
+                                double alpha, double beta, hipStream_t s) {
+  const auto ok = [](int w) { return w == 4 || w == 8 || w == 16; };
+  if (!ok(a.wg_waves) || !ok(a.wg_waves_p1) || !a.tm || (nvec != 2 && nvec != 4)) return hipErrorInvalidValue;
+  if (nvec == 2) {
+    if (a.n1 > 0) launch_phase_multi<T, 1, 2>(a, a.wg_waves_p1, (unsigned)a.n1, x, ldx, y, ldy, alpha, beta, s);
+    if (a.n2 > 0) launch_phase_multi<T, 2, 2>(a, a.wg_waves, (unsigned)a.n2, x, ldx, y, ldy, alpha, beta, s);
+  } else {
+    if (a.n1 > 0) launch_phase_multi<T, 1, 4>(a, a.wg_waves_p1, (unsigned)a.n1, x, ldx, y, ldy, alpha, beta, s);
+    if (a.n2 > 0) launch_phase_multi<T, 2, 4>(a, a.wg_waves, (unsigned)a.n2, x, ldx, y, ldy, alpha, beta, s);
+  }
   return hipGetLastError();
 }
 
@@ -435,6 +597,10 @@ template hipError_t launch_batched<float>(const BatchedArgs&, bool, int, const d
                                           hipStream_t, hipEvent_t*);
 template hipError_t launch_batched<double>(const BatchedArgs&, bool, int, const double*, double*, double, double,
                                            hipStream_t, hipEvent_t*);
+template hipError_t launch_batched_multi<float>(const BatchedArgs&, int, const double*, int64_t, double*, int64_t,
+                                                double, double, hipStream_t);
+template hipError_t launch_batched_multi<double>(const BatchedArgs&, int, const double*, int64_t, double*, int64_t,
+                                                 double, double, hipStream_t);
 template int persistent_blocks_per_cu<float>(int);
 template int persistent_blocks_per_cu<double>(int);
 template int phase1_blocks_per_cu<float>(int);

@@ -36,7 +36,11 @@ struct BatchedArgs {
   QueueCounters* ctr;
   int32_t wg_waves;     // waves per workgroup, phase-2 units (and the persistent launch)
   int32_t wg_waves_p1;  // waves per workgroup, phase-1 units
+  double* tm;           // intermediate values of the multi-vector product: kMultiMax segments of t_size
 };
+
+// Vectors a multi-vector product applies per pass over the factors.
+constexpr int kMultiMax = 4;
 
 // ev (optional): events recorded before the first launch, between the
 // launches and after the last one (plain and split: 3; persistent: 2).
@@ -47,6 +51,12 @@ hipError_t launch_plain(const PlainArgs& a, bool transpose, const double* x, dou
 template <typename T>
 hipError_t launch_batched(const BatchedArgs& a, bool persistent, int grid, const double* x, double* y, double alpha,
                           double beta, hipStream_t s, hipEvent_t* ev = nullptr);
+
+// Split schedule for nvec = 2 or 4 vectors at once: each panel entry is read
+// once for all of them.  x + r ldx -> y + r ldy (r < nvec).
+template <typename T>
+hipError_t launch_batched_multi(const BatchedArgs& a, int nvec, const double* x, int64_t ldx, double* y, int64_t ldy,
+                                double alpha, double beta, hipStream_t s);
 
 template <typename T>
 int persistent_blocks_per_cu(int wg_waves);

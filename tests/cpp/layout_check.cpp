@@ -51,12 +51,13 @@ static void check_pairs(const BatchedLayout<T>& L) {
     if (!seen[k]) die("unit in no pair", k);
 }
 
+// kStage: inputs staged per round (2048 for one vector; the multi-vector
+// product stages 2048 / R inputs of each of its R vectors).
 template <typename T>
 static double replay(const HostMatrix& H, int NW, int NW1, int64_t unit_bytes, const std::vector<double>& x,
                      const std::vector<double>& yref, int64_t split_slots = 0, int64_t* n_sums = nullptr,
-                     bool pairs = false) {
+                     bool pairs = false, int kStage = 2048) {
   constexpr int W = 16 / (int)sizeof(T);
-  constexpr int kStage = 2048;
   BatchedLayout<T> L = make_batched<T>(H, NW, unit_bytes, NW1, false, 0, split_slots, pairs);
   if (n_sums) *n_sums = (int64_t)L.sums.size() / 4;
   if (pairs) check_pairs(L);
@@ -277,6 +278,13 @@ int main(int argc, char** argv) {
     const double r32 = replay<float>(H, 8, NW1, 256 << 10, x, yref, 1 << 20, &ns32);
     std::printf("split NW1=%d sums %ld/%ld rel64=%.3e rel32=%.3e\n", NW1, (long)ns64, (long)ns32, r64, r32);
     if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed split product differs");
+  }
+  // staging rounds of the multi-vector product (2048 / R inputs per vector)
+  for (int R : {2, 4}) {
+    const double r64 = replay<double>(H, 8, 4, 256 << 10, x, yref, 0, nullptr, false, 2048 / R);
+    const double r32 = replay<float>(H, 8, 4, 256 << 10, x, yref, 1 << 20, nullptr, false, 2048 / R);
+    std::printf("rounds of %d inputs rel64=%.3e rel32=%.3e\n", 2048 / R, r64, r32);
+    if (!(r64 < 1e-13) || !(r32 < 1e-6)) die("replayed product with shorter rounds differs");
   }
   // inputs ordered in pairs of intervals (layouts of handles with ensemble buffers)
   for (int NW : {4, 8}) {

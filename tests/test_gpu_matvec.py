@@ -106,11 +106,14 @@ def test_independent_build_parity(torch_dev, hm, name):
 
 
 def test_alpha_beta_multi_rhs_and_ld(torch_dev, hm):
+    """Seven columns with a leading dimension beyond n: with the split
+    schedule a pass of four vectors, one of two, then one vector (each panel
+    entry read once per pass); every column against the oracle."""
     torch, dev = torch_dev
     w, f, g, H = oracle_case("dip30_48x24")
     B = oracle_blocks(H)
     rng = np.random.default_rng(21)
-    n, k, ld = f.n, 3, f.n + 5
+    n, k, ld = f.n, 7, f.n + 5
     X = rng.standard_normal((n, k))
     Y0 = rng.standard_normal((n, k))
     for kernel in KERNELS:
@@ -134,6 +137,33 @@ def test_alpha_beta_multi_rhs_and_ld(torch_dev, hm):
         assert torch.isfinite(y).all()
         # nrhs = 0 is a no-op
         Hg.matvec_raw(xbuf.data_ptr(), ybuf.data_ptr(), nrhs=0, ld=ld)
+        Hg.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_multi_vector_passes(torch_dev, hm, prec):
+    """The multi-vector product of the split schedule (passes of 4 and 2
+    vectors, forward and transposed, several wave counts) against the
+    oracle's products column by column, and against single-vector calls of
+    the same handle to rounding."""
+    torch, dev = torch_dev
+    w, f, g, H = oracle_case("dip30_150x70")
+    B = oracle_blocks(H)
+    rng = np.random.default_rng(22)
+    n, k = f.n, 6
+    X = 10.0 ** rng.uniform(-12, -9, (n, k))
+    tol = 1e-13 if prec == "f64" else 1e-6
+    for wg, wg1 in ((8, 4), (4, 16)):
+        Hg = hm.HMatrix.from_blocks(B["n"], B["perm"], B["desc"], B["off"], B["values"], prec=prec, kernel="split",
+                                    wg_waves=wg, wg_waves_p1=wg1)
+        Xd = torch.tensor(X, device=dev)
+        for tr in (False, True):
+            Y = (Hg.matvec_T(Xd) if tr else Hg.matvec(Xd)).cpu().numpy()
+            for c in range(k):
+                ref = H.matvec_T(X[:, c]) if tr else H.matvec(X[:, c])
+                assert rel(Y[:, c], ref) <= tol, (wg, wg1, tr, c)
+                y1 = (Hg.matvec_T(Xd[:, c].contiguous()) if tr else Hg.matvec(Xd[:, c].contiguous())).cpu().numpy()
+                assert rel(Y[:, c], y1) <= 1e-14
         Hg.close()
 
 

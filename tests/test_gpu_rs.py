@@ -233,6 +233,17 @@ def test_rk45_with_persistent_products(case):
         rk.attempt(y, D)
         rk.run(y, D, 19, use_graph=False)
         res.append((y.cpu().numpy(), D.cpu().numpy(), rk.state.accepted, rk.state.rejected, rk.t))
+    # the frozen-step replay is asynchronous: the binding reads the persistent
+    # schedule's wait flag after it (hmat_check), which must find it clear
+    reps = []
+    for H_ in (Hg, Hp):
+        rk = hm.RK45(H_, None, dp["a"], dp["b"], dp["dc"], p["V0"], p["f0"], p["eta_rad"], p["V_pl"])
+        y = torch.tensor(y0, device=dev)
+        D = torch.zeros(f.n, dtype=torch.float64, device=dev)
+        rk.replay(y, D, [1.0, 2.0, 4.0, 8.0, 16.0])
+        H_.check()
+        reps.append(y.cpu().numpy())
+    assert np.max(np.abs(reps[1] - reps[0])) <= 1e-10 * np.max(np.abs(reps[0]))
     Hp.close()
     (y1, D1, a1, r1, t1), (y2, D2, a2, r2, t2) = res
     assert (a1, r1) == (a2, r2) and t2 == pytest.approx(t1, rel=1e-12)
