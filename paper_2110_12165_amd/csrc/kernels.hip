@@ -152,10 +152,13 @@ __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ po
 
 // run_unit for R vectors at once (R = 2 or 4; split schedule): every panel
 // entry is read once and applied to the R vectors' inputs, which are staged
-// in LDS rows of kStage / R entries (vector r at zs[r * kStage / R]).  Vector
-// r reads x + r ldx, writes y + r ldy, and its intermediate values are
-// t + r ldt.  The sums of a row are taken in the same order as run_unit's
-// except for the shorter staging rounds.
+// in LDS rounds of kStageMulti inputs per vector (vector r at
+// zs[r * kStageMulti]; 1024 inputs, so that a typical phase-2 unit of
+// ~1700 inputs takes two rounds, not four as with 512).  Vector r reads
+// x + r ldx, writes y + r ldy, and its intermediate values are t + r ldt.
+// The sums of a row are taken in the same order as run_unit's except for
+// the shorter staging rounds.
+constexpr int kStageMulti = 1024;
 template <typename T, int NW, int R>
 __device__ __forceinline__ void run_unit_multi(const Unit& u, const T* __restrict__ pool, const double* __restrict__ x,
                                                int64_t ldx, double* __restrict__ y, int64_t ldy,
@@ -165,7 +168,7 @@ __device__ __forceinline__ void run_unit_multi(const Unit& u, const T* __restric
   using V = typename Pack<T>::vec;
   constexpr int W = Pack<T>::W;
   constexpr int U = 8;
-  constexpr int KSR = kStage / R;
+  constexpr int KSR = kStageMulti;
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int S = u.S, RG = u.RG;
@@ -272,7 +275,7 @@ template <typename T, int NW, int PHASE, int R>
 __global__ __launch_bounds__(NW * 64) void k_phase_multi(BatchedArgs a, const double* __restrict__ x, int64_t ldx,
                                                          double* __restrict__ y, int64_t ldy, double alpha,
                                                          double beta) {
-  __shared__ double zs[kStage];
+  __shared__ double zs[kStageMulti * R];
   __shared__ double red[R * NW * 64];
   const Unit u = a.units[(PHASE == 1 ? 0 : a.n1) + blockIdx.x];
   run_unit_multi<T, NW, R>(u, static_cast<const T*>(a.pool), x, ldx, y, ldy, a.perm, a.src, a.tm, a.t_size, a.sums,
