@@ -61,6 +61,68 @@ __device__ __forceinline__ double wave_sum(double v) {
 // ------------------------------------------------------------------------
 // batched layout
 // ------------------------------------------------------------------------
+// Stages inputs [c0, c0 + cl) of unit u in zs (FP64).  Each thread takes
+// inputs tid + k NW 64 in batches of kStageBatch: first every index (perm
+// or src), then every value, with no branch between the loads, so a batch
+// costs two memory round trips rather than two per input.  A padding input
+// (past nin in phase 1) reads t[0], the zero pad; an input whose value was
+// split over row parts adds the partials in part order, after the batch.
+constexpr int kStageBatch = 4;
+
+template <int NW, bool COHERENT>
+__device__ __forceinline__ void stage_inputs(const Unit& u, int c0, int cl, const double* __restrict__ x,
+                                             const int32_t* __restrict__ perm, const int32_t* __restrict__ src,
+                                             const double* t, const int32_t* __restrict__ sums, int t_size,
+                                             double* zs) {
+  constexpr int NT = NW * 64;
+  // inputs per thread per batch: every slot of a batch lies inside zs
+  // (kStage entries), so its values are stored without a bounds test
+  constexpr int B = kStageBatch * NT <= kStage ? kStageBatch : kStage / NT;
+  static_assert(B >= 1 && kStage % (B * NT) == 0, "staging batch");
+  const int tid = threadIdx.x;
+  // index list of the unit: phase 1 its rows (nin of them, then padding),
+  // phase 2 its input list (nin entries, padding included)
+  const int32_t* ip = (u.kind == 1 ? perm : src) + u.in0;
+  const int lim = u.nin;
+  for (int i0 = 0; i0 < cl; i0 += B * NT) {
+    int s[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int gi = c0 + i0 + k * NT + tid;
+      s[k] = ip[max(0, min(gi, lim - 1))];
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int gi = c0 + i0 + k * NT + tid;
+      if (gi >= lim) s[k] = -1;  // t[0]
+    }
+    double v[B];
+    bool split = false;
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int j = -s[k] - 1;
+      split |= j >= t_size;
+      const double* p = s[k] >= 0 ? x + s[k] : t + (j < t_size ? j : 0);
+      v[k] = COHERENT ? load_agent(p) : *p;
+    }
+    if (split) {  // a value split over row parts: partials added in part order
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int j = -s[k] - 1;
+        if (j >= t_size) {
+          const int* e = sums + 4 * (j - t_size);
+          if (COHERENT)
+            v[k] = ((load_agent(t + e[0]) + load_agent(t + e[1])) + load_agent(t + e[2])) + load_agent(t + e[3]);
+          else
+            v[k] = ((t[e[0]] + t[e[1]]) + t[e[2]]) + t[e[3]];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) zs[i0 + k * NT + tid] = v[k];  // past cl: never read
+  }
+}
+
 template <typename T, int NW, bool COHERENT>
 __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ pool, const double* __restrict__ x,
                                          double* __restrict__ y, const int32_t* __restrict__ perm,
@@ -84,27 +146,7 @@ __device__ __forceinline__ void run_unit(const Unit& u, const T* __restrict__ po
 
   for (int c0 = 0; c0 < nin_pad; c0 += kStage) {
     const int cl = min(kStage, nin_pad - c0);
-    for (int i = tid; i < cl; i += NW * 64) {
-      const int gi = c0 + i;
-      double v = 0.0;
-      if (u.kind == 1) {
-        if (gi < u.nin) v = x[perm[u.in0 + gi]];
-      } else {
-        const int s = src[u.in0 + gi];
-        if (s >= 0) {
-          v = x[s];
-        } else if (-s - 1 < t_size) {
-          v = COHERENT ? load_agent(t - s - 1) : t[-s - 1];
-        } else {  // a value split over row parts: partials added in part order
-          const int* e = sums + 4 * (-s - 1 - t_size);
-          if (COHERENT)
-            v = ((load_agent(t + e[0]) + load_agent(t + e[1])) + load_agent(t + e[2])) + load_agent(t + e[3]);
-          else
-            v = ((t[e[0]] + t[e[1]]) + t[e[2]]) + t[e[3]];
-        }
-      }
-      zs[i] = v;
-    }
+    stage_inputs<NW, COHERENT>(u, c0, cl, x, perm, src, t, sums, t_size, zs);
     __syncthreads();
     if (active) {
       const int q0 = c0 / W;
@@ -183,29 +225,45 @@ __device__ __forceinline__ void run_unit_multi(const Unit& u, const T* __restric
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r][0] = acc[r][1] = acc[r][2] = acc[r][3] = 0.0;
 
+  // staging as in stage_inputs, B inputs per thread and batch
+  constexpr int NT = NW * 64;
+  constexpr int B = KSR / NT >= 2 ? 2 : 1;
+  static_assert(KSR % (B * NT) == 0, "staging batch");
+  const int32_t* ip = (u.kind == 1 ? perm : src) + u.in0;
   for (int c0 = 0; c0 < nin_pad; c0 += KSR) {
     const int cl = min(KSR, nin_pad - c0);
-    for (int i = tid; i < cl; i += NW * 64) {
-      const int gi = c0 + i;
-      int sx = -1;  // t[0] is the zero pad
-      const int* e = nullptr;
-      if (u.kind == 1) {
-        if (gi < u.nin) sx = perm[u.in0 + gi];
-      } else {
-        const int s = src[u.in0 + gi];
-        if (s >= 0) sx = s;
-        else if (-s - 1 >= t_size) e = sums + 4 * (-s - 1 - t_size);
-        else sx = s;  // negative: -sx - 1 indexes t
+    for (int i0 = 0; i0 < cl; i0 += B * NT) {
+      int s[B];
+#pragma unroll
+      for (int k = 0; k < B; ++k) s[k] = ip[max(0, min(c0 + i0 + k * NT + tid, u.nin - 1))];
+#pragma unroll
+      for (int k = 0; k < B; ++k)
+        if (c0 + i0 + k * NT + tid >= u.nin) s[k] = -1;  // t[0]
+      double v[B][R];
+      bool split = false;
+#pragma unroll
+      for (int k = 0; k < B; ++k) {
+        const int j = -s[k] - 1;
+        split |= j >= t_size;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[k][r] = s[k] >= 0 ? x[r * ldx + s[k]] : t[r * ldt + (j < t_size ? j : 0)];
+      }
+      if (split) {
+#pragma unroll
+        for (int k = 0; k < B; ++k) {
+          const int j = -s[k] - 1;
+          if (j >= t_size) {
+            const int* e = sums + 4 * (j - t_size);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+              v[k][r] = ((t[r * ldt + e[0]] + t[r * ldt + e[1]]) + t[r * ldt + e[2]]) + t[r * ldt + e[3]];
+          }
+        }
       }
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double v;
-        if (e) v = ((t[r * ldt + e[0]] + t[r * ldt + e[1]]) + t[r * ldt + e[2]]) + t[r * ldt + e[3]];
-        else if (sx >= 0) v = x[r * ldx + sx];
-        else v = t[r * ldt + (-sx - 1)];
-        if (u.kind == 1 && gi >= u.nin) v = 0.0;
-        zs[r * KSR + i] = v;
-      }
+      for (int k = 0; k < B; ++k)
+#pragma unroll
+        for (int r = 0; r < R; ++r) zs[r * KSR + i0 + k * NT + tid] = v[k][r];  // past cl: never read
     }
     __syncthreads();
     if (active) {

@@ -87,9 +87,25 @@ static double replay(const HostMatrix& H, int NW, int NW1, int64_t unit_bytes, c
       const int nin_pad = u.nq * W;
       std::vector<double> zs(kStage), red((size_t)NWu * 64, 0.0);
       std::vector<double> acc((size_t)NWu * 64, 0.0);
+      if (u.kind == 2 && u.nin != nin_pad) die("phase-2 input list not padded to its groups", u.nin, nin_pad);
       for (int c0 = 0; c0 < nin_pad; c0 += kStage) {
         const int cl = std::min(kStage, nin_pad - c0);
         if (cl % W) die("stage not a multiple of W", cl);
+        {
+          // the kernels stage in batches of B inputs per thread (single vector:
+          // up to 4; multi-vector: 2, or 1 when a round has one input per
+          // thread): index loads clamped to the unit's list, LDS slots below kStage
+          const int NT = NWu * 64;
+          const int B = kStage == 2048 ? std::min(4, kStage / NT) : (kStage / NT >= 2 ? 2 : 1);
+          if (B < 1 || kStage % (B * NT) != 0) die("staging batch", B, NT);
+          for (int i0 = 0; i0 < cl; i0 += B * NT)
+            for (int i = i0; i < i0 + B * NT; ++i) {
+              if (i >= kStage) die("stage slot", i);
+              const int gi = c0 + i;
+              const int64_t idx = (int64_t)u.in0 + std::max(0, std::min(gi, u.nin - 1));
+              if (u.kind == 1 ? idx >= n : idx >= (int64_t)L.src.size()) die("clamped index load", (long)idx);
+            }
+        }
         for (int i = 0; i < cl; ++i) {
           const int gi = c0 + i;
           double v = 0.0;
