@@ -58,15 +58,30 @@ def test_full_size_against_exact_product(setup, variant):
     y1 = H.matvec(xd).cpu().numpy()
     y2 = H.matvec(xd).cpu().numpy()
     yT = H.matvec_T(xd).cpu().numpy()             # the same handle's H^T x (A is symmetric)
+    tol = 1e-6 if opts["prec"] == "f64" else 2e-5
+    if variant != "plain_f64":
+        # six vectors: a pass of 4 and a pass of 2 through the factors (the
+        # multi-vector product bench.py times), forward and transposed, each
+        # column against its exact product
+        Xm = np.stack([x] + [loguniform_rates(f.n, 40 + c) for c in range(5)], axis=1)
+        Xd = torch.tensor(Xm, device=dev)
+        Ym = H.matvec(Xd).cpu().numpy()
+        YmT = H.matvec_T(Xd).cpu().numpy()
+        for c in range(Xm.shape[1]):
+            yc = y_exact if c == 0 else fft_grid_product(f.nx, f.ny, f.h, f.slip, MU, NU, Xm[:, c])
+            rc, rcT = rel(Ym[:, c], yc), rel(YmT[:, c], yc)
+            say(f"    vector {c} of 6: rel vs exact {rc:.3e}, transposed {rcT:.3e}")
+            assert rc <= tol and rcT <= tol, c
+        assert rel(Ym[:, 0], y1) <= 1e-14 and rel(YmT[:, 0], yT) <= 1e-14
     info = H.info()
     H.close()
     r = rel(y1, y_exact)
     say(f"    rel vs exact {r:.3e}  entries {info['dense_entries'] + info['lr_entries']}")
-    assert r <= (1e-6 if opts["prec"] == "f64" else 2e-5)
+    assert r <= tol
     assert np.array_equal(y1, y2)                 # run-to-run reproducible
     rT = rel(yT, y_exact)
     say(f"    transposed product: rel vs exact {rT:.3e}")
-    assert rT <= (1e-6 if opts["prec"] == "f64" else 2e-5)
+    assert rT <= tol
     # sampled rows, evaluated one by one from the entries
     g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
     rows = np.random.default_rng(99).choice(f.n, 48, replace=False)
