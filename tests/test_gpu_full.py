@@ -225,3 +225,26 @@ def test_integration_against_oracle(setup):
     assert max(errs["batched_f64"]) <= 1e-8
     assert max(errs["batched_f32"]) <= 1e-5
     assert gpu_rej == rej and drift <= 1e-3
+
+
+@pytest.mark.parametrize("name,lattice", [("dip30_120x64", 32), ("dip30_240x128", 32), ("dip30_960x512", 32),
+                                          ("dip30_480x256", 1), ("dip30_480x256", 8)])
+def test_sweep_configurations_against_exact_product(setup, name, lattice):
+    """The size and lattice sweeps bench.py times (N = 7680 ... 491520 at
+    lattice 32, the largest being the maximum size measured; lattice 1, the
+    normal H-matrix, and 8 at N = 122880), in their launch configuration
+    (device construction, FP32 split schedule), against the oracle's exact
+    product of each grid."""
+    torch, hm = setup[0], setup[1]
+    w = WORKLOADS[name]
+    f = config_fault(name)
+    say(f"[sweep] {name} N={f.n} lattice {lattice}")
+    H = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, aca_eps=w["aca_eps"], eta=w["eta"], leaf=w["leaf"],
+                         lattice=lattice, prec="f32", kernel="split", transpose=0, build_device=1)
+    x = loguniform_rates(f.n, w["seed"])
+    y = H.matvec(torch.tensor(x, device=torch.device("cuda:0"))).cpu().numpy()
+    H.close()
+    torch.cuda.empty_cache()
+    r = rel(y, fft_grid_product(f.nx, f.ny, f.h, f.slip, MU, NU, x))
+    say(f"    rel vs exact {r:.3e}")
+    assert r <= 2e-5
