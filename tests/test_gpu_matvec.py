@@ -196,10 +196,17 @@ def test_degenerate_sizes(torch_dev, hm):
         g = CoplanarRectGeometry(f.verts, f.slip_dir, MU, NU)
         A = dense_matrix(g)
         x = loguniform_rates(f.n, 3)
+        X = loguniform_rates(f.n, 4, nrhs=6)
         for kernel in KERNELS:
             Hg = hm.HMatrix.build(f.verts, f.slip_dir, MU, NU, leaf=leaf, kernel=kernel)
             y = Hg.matvec(torch.tensor(x, device=dev)).cpu().numpy()
             assert rel(y, A @ x) <= 1e-6, (nx, ny, kernel)
+            # six vectors (passes of 4 and 2 on the split schedule), forward and transposed
+            Xd = torch.tensor(X, device=dev)
+            Y, YT = Hg.matvec(Xd).cpu().numpy(), Hg.matvec_T(Xd).cpu().numpy()
+            for c in range(X.shape[1]):
+                assert rel(Y[:, c], A @ X[:, c]) <= 1e-6, (nx, ny, kernel, c)
+                assert rel(YT[:, c], A.T @ X[:, c]) <= 1e-6, (nx, ny, kernel, c)
             Hg.close()
 
 
